@@ -1,0 +1,525 @@
+/*
+ * cbct_oracle.c -- plain FP64 CPU oracle for the circular-orbit cone-beam
+ * projector pair (TEST INFRASTRUCTURE ONLY).
+ *
+ * Only tests, the smoke check and the CPU-baseline leg of the benchmark load
+ * this file's shared library.  It shares no code, header, table or constant
+ * with the HIP library: every quantity below is recomputed from the
+ * definitions, in double precision, one ray or one voxel at a time.
+ *
+ * What is computed (paper, Sec. 2.2, definition of the cone-beam transform
+ * P(mu)(t,u) = integral of mu over the line from the source to detector
+ * element u at time t, and its adjoint, the backprojection P*):
+ *
+ *   World frame: isocenter at the origin, rotation axis z.  For angle theta
+ *     source      S  = sid (cos th, sin th, 0)
+ *     e_u         = (-sin th, cos th, 0)     (direction of source motion)
+ *     e_v         = (0, 0, 1)
+ *     detector    D  = -(sdd - sid)(cos th, sin th, 0) + off_u e_u + off_v e_v
+ *     pixel       P(iu,iv) = D + (iu - (nu-1)/2) du e_u + (iv - (nv-1)/2) dv e_v
+ *   (Sec. 2.2: source-isocenter 1000 mm, isocenter-detector 536 mm, detector
+ *   offset to the side in the direction of rotation.)
+ *   Voxel centres: c(i,j,k) = origin + ((i-(nx-1)/2) vx, (j-(ny-1)/2) vy,
+ *   (k-(nz-1)/2) vz); memory index (k*ny + j)*nx + i.
+ *
+ *   Discrete line integral (the paper states only the continuous integral;
+ *   this is the discretisation the whole repository defines): ray direction
+ *   d = P - S.  Its major axis m is x when |d_x| >= |d_y|, else y.  The ray is
+ *   sampled exactly where it crosses the voxel-centre planes of m, strictly
+ *   between source and pixel (0 < t < 1); on such a plane the trilinear
+ *   interpolant of the zero-padded volume reduces to bilinear interpolation
+ *   in the two remaining axes.  The ray value is the sum of the samples times
+ *   the length of ray per plane spacing, ds = vox_m |d| / |d_m|.
+ *
+ *   The adjoint is the Euclidean transpose: x_v = sum_r A[r,v] y_r.
+ *
+ * Everything is FP64.  Parallel loops (OpenMP) only split independent rays;
+ * the scatter adjoint keeps one accumulator volume per thread and sums them
+ * in thread order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double sid, sdd;          /* source-isocenter, source-detector distance (mm) */
+    int n_angles;
+    const double *angles;     /* n_angles source angles (rad) */
+    int nu, nv;               /* detector columns (along e_u), rows (along e_v) */
+    double du, dv;            /* detector pitch (mm) */
+    double off_u, off_v;      /* detector centre offset along e_u, e_v (mm) */
+    int nx, ny, nz;           /* voxel counts */
+    double vx, vy, vz;        /* voxel pitch (mm) */
+    double ox, oy, oz;        /* volume centre (mm, relative to isocenter) */
+} orc_geom;
+
+/* ---- ray geometry ------------------------------------------------------ */
+
+/* Source position and direction d = P(iu,iv) - S for angle index a. */
+void orc_ray(const orc_geom *g, int a, int iu, int iv, double S[3], double d[3])
+{
+    double th = g->angles[a];
+    double c = cos(th), s = sin(th);
+    double eu[3] = {-s, c, 0.0};
+    double ev[3] = {0.0, 0.0, 1.0};
+    double D[3], P[3];
+    double pu = (iu - 0.5 * (g->nu - 1)) * g->du;
+    double pv = (iv - 0.5 * (g->nv - 1)) * g->dv;
+    S[0] = g->sid * c;
+    S[1] = g->sid * s;
+    S[2] = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        double toward = (q == 0) ? c : (q == 1) ? s : 0.0;
+        D[q] = -(g->sdd - g->sid) * toward + g->off_u * eu[q] + g->off_v * ev[q];
+        P[q] = D[q] + pu * eu[q] + pv * ev[q];
+        d[q] = P[q] - S[q];
+    }
+}
+
+static double norm3(const double d[3])
+{
+    return sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+}
+
+static double centre(int idx, int n, double pitch, double org)
+{
+    return org + (idx - 0.5 * (n - 1)) * pitch;
+}
+
+/* Fractional voxel index of world coordinate w along an axis. */
+static double findex(double w, int n, double pitch, double org)
+{
+    return (w - org) / pitch + 0.5 * (n - 1);
+}
+
+static double hat(double s)
+{
+    double a = 1.0 - fabs(s);
+    return a > 0.0 ? a : 0.0;
+}
+
+/* Volume value with zero padding. */
+static double vox(const orc_geom *g, const double *vol, long i, long j, long k)
+{
+    if (i < 0 || j < 0 || k < 0 || i >= g->nx || j >= g->ny || k >= g->nz)
+        return 0.0;
+    return vol[(k * g->ny + j) * (long)g->nx + i];
+}
+
+/*
+ * Visit every sample of ray (a,iu,iv).  For each plane crossing that lies
+ * strictly between source and pixel and inside the open support
+ * (-1, n) of both in-plane fractional indices, call visit() with the plane
+ * index, the two in-plane fractional indices and ds.  Returns the sample
+ * count.  The visitor receives the in-plane pair as (x-or-y index, z index).
+ */
+typedef void (*sample_fn)(void *ctx, int major_is_x, int p, double f1, double fz);
+
+static long walk_ray(const orc_geom *g, int a, int iu, int iv, double *ds_out,
+                     sample_fn visit, void *ctx)
+{
+    double S[3], d[3];
+    orc_ray(g, a, iu, iv, S, d);
+    int major_is_x = fabs(d[0]) >= fabs(d[1]);
+    int m = major_is_x ? 0 : 1;        /* sampled axis */
+    int o = major_is_x ? 1 : 0;        /* other in-plane axis */
+    int nm = major_is_x ? g->nx : g->ny;
+    int no = major_is_x ? g->ny : g->nx;
+    double pm = major_is_x ? g->vx : g->vy;
+    double po = major_is_x ? g->vy : g->vx;
+    double om = major_is_x ? g->ox : g->oy;
+    double oo = major_is_x ? g->oy : g->ox;
+    *ds_out = pm * norm3(d) / fabs(d[m]);
+    long count = 0;
+    for (int p = 0; p < nm; ++p) {
+        double cm = centre(p, nm, pm, om);
+        double t = (cm - S[m]) / d[m];
+        if (!(t > 0.0 && t < 1.0))
+            continue;
+        double qo = S[o] + t * d[o];
+        double qz = S[2] + t * d[2];
+        double f1 = findex(qo, no, po, oo);
+        double fz = findex(qz, g->nz, g->vz, g->oz);
+        if (!(f1 > -1.0 && f1 < no && fz > -1.0 && fz < g->nz))
+            continue;
+        ++count;
+        if (visit)
+            visit(ctx, major_is_x, p, f1, fz);
+    }
+    return count;
+}
+
+/* ---- forward ----------------------------------------------------------- */
+
+typedef struct {
+    const orc_geom *g;
+    const double *vol;
+    double acc;
+} fwd_ctx;
+
+static void fwd_visit(void *vctx, int major_is_x, int p, double f1, double fz)
+{
+    fwd_ctx *c = (fwd_ctx *)vctx;
+    long j0 = (long)floor(f1), k0 = (long)floor(fz);
+    double s = 0.0;
+    for (long dj = 0; dj <= 1; ++dj)
+        for (long dk = 0; dk <= 1; ++dk) {
+            long jj = j0 + dj, kk = k0 + dk;
+            double w = hat(f1 - jj) * hat(fz - kk);
+            double v = major_is_x ? vox(c->g, c->vol, p, jj, kk) : vox(c->g, c->vol, jj, p, kk);
+            s += w * v;
+        }
+    c->acc += s;
+}
+
+static double forward_ray(const orc_geom *g, const double *vol, int a, int iu, int iv)
+{
+    fwd_ctx c = {g, vol, 0.0};
+    double ds;
+    walk_ray(g, a, iu, iv, &ds, fwd_visit, &c);
+    return c.acc * ds;
+}
+
+/* sino[(a*nv + iv)*nu + iu] = (A vol) */
+int orc_forward(const orc_geom *g, const double *vol, double *sino, int nthreads)
+{
+    long nrow = (long)g->n_angles * g->nv;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (long r = 0; r < nrow; ++r) {
+        int a = (int)(r / g->nv), iv = (int)(r % g->nv);
+        for (int iu = 0; iu < g->nu; ++iu)
+            sino[r * g->nu + iu] = forward_ray(g, vol, a, iu, iv);
+    }
+    return 0;
+}
+
+/* Forward values for an explicit list of flat ray indices (a*nv+iv)*nu+iu. */
+int orc_forward_rays(const orc_geom *g, const double *vol, const int64_t *rays, int64_t n,
+                     double *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t r = rays[q];
+        int iu = (int)(r % g->nu);
+        int iv = (int)((r / g->nu) % g->nv);
+        int a = (int)(r / ((int64_t)g->nu * g->nv));
+        out[q] = forward_ray(g, vol, a, iu, iv);
+    }
+    return 0;
+}
+
+/* ---- adjoint, scatter form --------------------------------------------- */
+
+typedef struct {
+    const orc_geom *g;
+    double *vol;
+    double yds;   /* y_r * ds_r */
+} adj_ctx;
+
+static void adj_visit(void *vctx, int major_is_x, int p, double f1, double fz)
+{
+    adj_ctx *c = (adj_ctx *)vctx;
+    const orc_geom *g = c->g;
+    long j0 = (long)floor(f1), k0 = (long)floor(fz);
+    for (long dj = 0; dj <= 1; ++dj)
+        for (long dk = 0; dk <= 1; ++dk) {
+            long jj = j0 + dj, kk = k0 + dk;
+            long ii = major_is_x ? p : jj;
+            long yy = major_is_x ? jj : p;
+            if (ii < 0 || yy < 0 || kk < 0 || ii >= g->nx || yy >= g->ny || kk >= g->nz)
+                continue;
+            double w = hat(f1 - jj) * hat(fz - kk);
+            c->vol[(kk * g->ny + yy) * (long)g->nx + ii] += w * c->yds;
+        }
+}
+
+/* vol = A^T sino, by scattering every ray's samples (one accumulator volume
+ * per thread, summed in thread order afterwards). */
+int orc_adjoint(const orc_geom *g, const double *sino, double *vol, int nthreads)
+{
+    long nvox = (long)g->nx * g->ny * g->nz;
+    long nrow = (long)g->n_angles * g->nv;
+    int nt = 1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+    nt = omp_get_max_threads();
+#endif
+    double *part = (double *)calloc((size_t)nt * (size_t)nvox, sizeof(double));
+    if (!part)
+        return -1;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *mine = part + (size_t)tid * (size_t)nvox;
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+        for (long r = 0; r < nrow; ++r) {
+            int a = (int)(r / g->nv), iv = (int)(r % g->nv);
+            for (int iu = 0; iu < g->nu; ++iu) {
+                double y = sino[r * g->nu + iu];
+                if (y == 0.0)
+                    continue;
+                double S[3], d[3], ds;
+                orc_ray(g, a, iu, iv, S, d);
+                int major_is_x = fabs(d[0]) >= fabs(d[1]);
+                double pm = major_is_x ? g->vx : g->vy;
+                adj_ctx c = {g, mine, y * pm * norm3(d) / fabs(d[major_is_x ? 0 : 1])};
+                walk_ray(g, a, iu, iv, &ds, adj_visit, &c);
+            }
+        }
+    }
+    for (long v = 0; v < nvox; ++v) {
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t)
+            s += part[(size_t)t * (size_t)nvox + v];
+        vol[v] = s;
+    }
+    free(part);
+    return 0;
+}
+
+/* ---- adjoint, gather form for selected voxels --------------------------- */
+
+/* Detector coordinates (fractional column, row) of world point w at angle a,
+ * by intersecting the line S->w with the detector plane. */
+static void project_point(const orc_geom *g, int a, const double w[3], double *fu, double *fv)
+{
+    double th = g->angles[a];
+    double c = cos(th), s = sin(th);
+    double S[3] = {g->sid * c, g->sid * s, 0.0};
+    double r[3] = {w[0] - S[0], w[1] - S[1], w[2] - S[2]};
+    double depth = r[0] * c + r[1] * s;        /* along (cos, sin): -sdd at the panel */
+    double lam = -g->sdd / depth;
+    double U = lam * (r[0] * (-s) + r[1] * c);
+    double V = lam * r[2];
+    *fu = (U - g->off_u) / g->du + 0.5 * (g->nu - 1);
+    *fv = (V - g->off_v) / g->dv + 0.5 * (g->nv - 1);
+}
+
+/* Weight A[r, v] of voxel (i,j,k) in ray (a,iu,iv), from the definition. */
+double orc_weight(const orc_geom *g, int a, int iu, int iv, int i, int j, int k)
+{
+    double S[3], d[3];
+    orc_ray(g, a, iu, iv, S, d);
+    int major_is_x = fabs(d[0]) >= fabs(d[1]);
+    int m = major_is_x ? 0 : 1, o = major_is_x ? 1 : 0;
+    int p = major_is_x ? i : j, q = major_is_x ? j : i;
+    int nm = major_is_x ? g->nx : g->ny, no = major_is_x ? g->ny : g->nx;
+    double pm = major_is_x ? g->vx : g->vy, po = major_is_x ? g->vy : g->vx;
+    double om = major_is_x ? g->ox : g->oy, oo = major_is_x ? g->oy : g->ox;
+    double t = (centre(p, nm, pm, om) - S[m]) / d[m];
+    if (!(t > 0.0 && t < 1.0))
+        return 0.0;
+    double f1 = findex(S[o] + t * d[o], no, po, oo);
+    double fz = findex(S[2] + t * d[2], g->nz, g->vz, g->oz);
+    if (!(f1 > -1.0 && f1 < no && fz > -1.0 && fz < g->nz))
+        return 0.0;
+    double ds = pm * norm3(d) / fabs(d[m]);
+    return ds * hat(f1 - q) * hat(fz - k);
+}
+
+/*
+ * out[q] = (A^T sino)[vox[q]] for flat voxel indices (k*ny+j)*nx+i, by
+ * gathering over every ray whose weight at the voxel can be non-zero.  Those
+ * rays pass within one voxel pitch of the centre along each axis, so they
+ * hit the detector inside the projection of the box centre +- pitch; the
+ * window scanned is that projection's bounding box widened by two pixels,
+ * and the function returns -2 if any weight on the window's border is
+ * non-zero (the window would then have been too small).
+ */
+int orc_adjoint_voxels(const orc_geom *g, const double *sino, const int64_t *voxels, int64_t n,
+                       double *out, int nthreads)
+{
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+#endif
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t v = voxels[q];
+        int i = (int)(v % g->nx);
+        int j = (int)((v / g->nx) % g->ny);
+        int k = (int)(v / ((int64_t)g->nx * g->ny));
+        double c[3] = {centre(i, g->nx, g->vx, g->ox), centre(j, g->ny, g->vy, g->oy),
+                       centre(k, g->nz, g->vz, g->oz)};
+        double acc = 0.0;
+        for (int a = 0; a < g->n_angles; ++a) {
+            double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+            for (int corner = 0; corner < 8; ++corner) {
+                double w[3] = {c[0] + ((corner & 1) ? g->vx : -g->vx),
+                               c[1] + ((corner & 2) ? g->vy : -g->vy),
+                               c[2] + ((corner & 4) ? g->vz : -g->vz)};
+                double fu, fv;
+                project_point(g, a, w, &fu, &fv);
+                umin = fmin(umin, fu); umax = fmax(umax, fu);
+                vmin = fmin(vmin, fv); vmax = fmax(vmax, fv);
+            }
+            int u0 = (int)floor(umin) - 2, u1 = (int)ceil(umax) + 2;
+            int v0 = (int)floor(vmin) - 2, v1 = (int)ceil(vmax) + 2;
+            for (int iv = v0; iv <= v1; ++iv) {
+                if (iv < 0 || iv >= g->nv)
+                    continue;
+                for (int iu = u0; iu <= u1; ++iu) {
+                    if (iu < 0 || iu >= g->nu)
+                        continue;
+                    double w = orc_weight(g, a, iu, iv, i, j, k);
+                    if (w == 0.0)
+                        continue;
+                    if (iu == u0 || iu == u1 || iv == v0 || iv == v1)
+                        bad = 1;
+                    acc += w * sino[((int64_t)a * g->nv + iv) * g->nu + iu];
+                }
+            }
+        }
+        out[q] = acc;
+    }
+    return bad ? -2 : 0;
+}
+
+/* ---- sample count ------------------------------------------------------ */
+
+/* Number of (ray, plane) pairs with non-empty support, the unit of work. */
+int64_t orc_sample_count(const orc_geom *g, int nthreads)
+{
+    int64_t total = 0;
+    long nrow = (long)g->n_angles * g->nv;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : total)
+#endif
+    for (long r = 0; r < nrow; ++r) {
+        int a = (int)(r / g->nv), iv = (int)(r % g->nv);
+        for (int iu = 0; iu < g->nu; ++iu) {
+            double ds;
+            total += walk_ray(g, a, iu, iv, &ds, NULL, NULL);
+        }
+    }
+    return total;
+}
+
+/* ---- independent references for the pins -------------------------------- */
+
+/* Segment parameter interval [t0,t1] of S + t d inside box [lo,hi] (slab
+ * clipping), intersected with [tmin,tmax].  Returns 0 if empty. */
+static int clip_box(const double S[3], const double d[3], const double lo[3], const double hi[3],
+                    double tmin, double tmax, double *t0, double *t1)
+{
+    double a = tmin, b = tmax;
+    for (int q = 0; q < 3; ++q) {
+        if (d[q] == 0.0) {
+            if (S[q] < lo[q] || S[q] > hi[q])
+                return 0;
+            continue;
+        }
+        double ta = (lo[q] - S[q]) / d[q], tb = (hi[q] - S[q]) / d[q];
+        if (ta > tb) {
+            double tmp = ta; ta = tb; tb = tmp;
+        }
+        if (ta > a) a = ta;
+        if (tb < b) b = tb;
+    }
+    *t0 = a;
+    *t1 = b;
+    return b > a;
+}
+
+/* Exact length (mm) of ray (a,iu,iv) inside the axis-aligned box [lo,hi]. */
+double orc_chord_box(const orc_geom *g, int a, int iu, int iv, const double lo[3], const double hi[3])
+{
+    double S[3], d[3], t0, t1;
+    orc_ray(g, a, iu, iv, S, d);
+    if (!clip_box(S, d, lo, hi, 0.0, 1.0, &t0, &t1))
+        return 0.0;
+    return (t1 - t0) * norm3(d);
+}
+
+/*
+ * Brute-force Siddon matrix: L[r*nvox + v] = exact length of ray r inside the
+ * cube of voxel v (every ray is clipped against every voxel box).  Tiny
+ * volumes only.
+ */
+int orc_siddon_dense(const orc_geom *g, double *L)
+{
+    long nvox = (long)g->nx * g->ny * g->nz;
+    long nray = (long)g->n_angles * g->nv * g->nu;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (long r = 0; r < nray; ++r) {
+        int iu = (int)(r % g->nu), iv = (int)((r / g->nu) % g->nv), a = (int)(r / ((long)g->nu * g->nv));
+        for (long v = 0; v < nvox; ++v) {
+            int i = (int)(v % g->nx), j = (int)((v / g->nx) % g->ny), k = (int)(v / ((long)g->nx * g->ny));
+            double c[3] = {centre(i, g->nx, g->vx, g->ox), centre(j, g->ny, g->vy, g->oy),
+                           centre(k, g->nz, g->vz, g->oz)};
+            double lo[3] = {c[0] - 0.5 * g->vx, c[1] - 0.5 * g->vy, c[2] - 0.5 * g->vz};
+            double hi[3] = {c[0] + 0.5 * g->vx, c[1] + 0.5 * g->vy, c[2] + 0.5 * g->vz};
+            L[r * nvox + v] = orc_chord_box(g, a, iu, iv, lo, hi);
+        }
+    }
+    return 0;
+}
+
+/*
+ * Exact line integral, over the whole source-to-pixel segment, of the
+ * trilinear interpolant of the zero-padded volume.  The interpolant is a
+ * trilinear polynomial inside each dual cell (the box spanned by eight
+ * neighbouring voxel centres, pad layer included), so along a straight
+ * segment it is a cubic in t; two-point Gauss-Legendre per cell segment
+ * integrates it exactly.  Cells are visited by clipping the ray against
+ * every dual cell of the padded grid (small volumes only).
+ */
+double orc_interp_integral(const orc_geom *g, const double *vol, int a, int iu, int iv)
+{
+    double S[3], d[3];
+    orc_ray(g, a, iu, iv, S, d);
+    double len = norm3(d);
+    const double gl = 0.5 / sqrt(3.0);
+    double total = 0.0;
+    for (int k = -1; k < g->nz; ++k)
+        for (int j = -1; j < g->ny; ++j)
+            for (int i = -1; i < g->nx; ++i) {
+                double lo[3] = {centre(i, g->nx, g->vx, g->ox), centre(j, g->ny, g->vy, g->oy),
+                                centre(k, g->nz, g->vz, g->oz)};
+                double hi[3] = {lo[0] + g->vx, lo[1] + g->vy, lo[2] + g->vz};
+                double t0, t1;
+                if (!clip_box(S, d, lo, hi, 0.0, 1.0, &t0, &t1))
+                    continue;
+                double seg = 0.0;
+                for (int n = 0; n < 2; ++n) {
+                    double t = 0.5 * (t0 + t1) + (n ? gl : -gl) * (t1 - t0);
+                    double x = (S[0] + t * d[0] - lo[0]) / g->vx;
+                    double y = (S[1] + t * d[1] - lo[1]) / g->vy;
+                    double z = (S[2] + t * d[2] - lo[2]) / g->vz;
+                    double f = 0.0;
+                    for (int c = 0; c < 8; ++c) {
+                        int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+                        double w = (bx ? x : 1 - x) * (by ? y : 1 - y) * (bz ? z : 1 - z);
+                        f += w * vox(g, vol, i + bx, j + by, k + bz);
+                    }
+                    seg += 0.5 * f;
+                }
+                total += seg * (t1 - t0) * len;
+            }
+    return total;
+}

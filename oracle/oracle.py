@@ -1,0 +1,300 @@
+"""FP64 CPU oracle for the cone-beam projector pair -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The product path (the HIP library and its
+Python binding) never imports it and shares no code with it.
+
+Contents, each written from the paper (arXiv 2512.21180):
+
+* ``forward`` / ``adjoint`` / ``forward_rays`` / ``adjoint_voxels`` /
+  ``sample_count``: the discretised cone-beam transform P and its transpose
+  (Sec. 2.2, definition of the projection operator and of the backprojection
+  as its adjoint), implemented in plain C (``cbct_oracle.c``) in FP64.
+* ``ray``, ``weight``, ``chord_box``, ``siddon_dense``, ``interp_integral``:
+  independent references used by the pins (exact chord lengths, brute-force
+  path lengths, exact line integrals of the trilinear interpolant).
+* ``dense_matrix``: A built column by column from unit volumes.
+* ``cgls`` / ``landweber``: FP64 least-squares solvers on top of the oracle
+  operators; Landweber uses the gradient term P*(P x - y) of Alg. 1.
+
+Geometry is passed as a plain dict with keys sid, sdd, n_angles, angles
+(optional, radians), nu, nv, du, dv, off_u, off_v, nx, ny, nz, vx, vy, vz,
+origin (3-tuple, mm).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cbct_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C source into ``oracle/liboracle.so`` with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _OGeom(ctypes.Structure):
+    _fields_ = [
+        ("sid", ctypes.c_double), ("sdd", ctypes.c_double),
+        ("n_angles", ctypes.c_int), ("angles", ctypes.POINTER(ctypes.c_double)),
+        ("nu", ctypes.c_int), ("nv", ctypes.c_int),
+        ("du", ctypes.c_double), ("dv", ctypes.c_double),
+        ("off_u", ctypes.c_double), ("off_v", ctypes.c_double),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("vx", ctypes.c_double), ("vy", ctypes.c_double), ("vz", ctypes.c_double),
+        ("ox", ctypes.c_double), ("oy", ctypes.c_double), ("oz", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        d, i64 = ctypes.c_double, ctypes.c_int64
+        G = P(_OGeom)
+        lib.orc_ray.argtypes = [G, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(d), P(d)]
+        lib.orc_forward.argtypes = [G, P(d), P(d), ctypes.c_int]
+        lib.orc_adjoint.argtypes = [G, P(d), P(d), ctypes.c_int]
+        lib.orc_forward_rays.argtypes = [G, P(d), P(i64), i64, P(d), ctypes.c_int]
+        lib.orc_adjoint_voxels.argtypes = [G, P(d), P(i64), i64, P(d), ctypes.c_int]
+        lib.orc_sample_count.argtypes = [G, ctypes.c_int]
+        lib.orc_sample_count.restype = i64
+        lib.orc_weight.argtypes = [G] + [ctypes.c_int] * 6
+        lib.orc_weight.restype = d
+        lib.orc_chord_box.argtypes = [G, ctypes.c_int, ctypes.c_int, ctypes.c_int, P(d), P(d)]
+        lib.orc_chord_box.restype = d
+        lib.orc_siddon_dense.argtypes = [G, P(d)]
+        lib.orc_interp_integral.argtypes = [G, P(d), ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.orc_interp_integral.restype = d
+        _lib = lib
+    return _lib
+
+
+def angles_of(g: dict) -> np.ndarray:
+    """Source angles: the explicit list if given, else 2*pi*a/n (a = 0..n-1)."""
+    if g.get("angles") is not None:
+        a = np.asarray(g["angles"], dtype=np.float64)
+        assert a.shape == (g["n_angles"],)
+        return a
+    n = g["n_angles"]
+    return 2.0 * np.pi * np.arange(n, dtype=np.float64) / n
+
+
+class _Geom:
+    """ctypes view of a geometry dict; keeps the angle array alive."""
+
+    def __init__(self, g: dict):
+        self.angles = np.ascontiguousarray(angles_of(g))
+        o = g.get("origin", (0.0, 0.0, 0.0))
+        self.s = _OGeom(
+            float(g["sid"]), float(g["sdd"]), int(g["n_angles"]),
+            self.angles.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            int(g["nu"]), int(g["nv"]), float(g["du"]), float(g["dv"]),
+            float(g.get("off_u", 0.0)), float(g.get("off_v", 0.0)),
+            int(g["nx"]), int(g["ny"]), int(g["nz"]),
+            float(g["vx"]), float(g["vy"]), float(g["vz"]),
+            float(o[0]), float(o[1]), float(o[2]),
+        )
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def vol_shape(g: dict):
+    return (g["nz"], g["ny"], g["nx"])
+
+
+def sino_shape(g: dict):
+    return (g["n_angles"], g["nv"], g["nu"])
+
+
+def forward(g: dict, vol: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """Sinogram [n_angles][nv][nu] = A vol (vol is [nz][ny][nx])."""
+    lib = _load()
+    G = _Geom(g)
+    x = np.ascontiguousarray(vol, dtype=np.float64)
+    assert x.shape == vol_shape(g)
+    y = np.zeros(sino_shape(g), dtype=np.float64)
+    lib.orc_forward(G.ref, _dp(x), _dp(y), nthreads)
+    return y
+
+
+def adjoint(g: dict, sino: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """Volume [nz][ny][nx] = A^T sino (scatter form)."""
+    lib = _load()
+    G = _Geom(g)
+    y = np.ascontiguousarray(sino, dtype=np.float64)
+    assert y.shape == sino_shape(g)
+    x = np.zeros(vol_shape(g), dtype=np.float64)
+    rc = lib.orc_adjoint(G.ref, _dp(y), _dp(x), nthreads)
+    if rc != 0:
+        raise MemoryError("oracle adjoint could not allocate its accumulators")
+    return x
+
+
+def forward_rays(g: dict, vol: np.ndarray, rays: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """A vol at flat ray indices (a*nv + iv)*nu + iu."""
+    lib = _load()
+    G = _Geom(g)
+    x = np.ascontiguousarray(vol, dtype=np.float64)
+    r = np.ascontiguousarray(rays, dtype=np.int64)
+    out = np.zeros(r.shape[0], dtype=np.float64)
+    lib.orc_forward_rays(G.ref, _dp(x), _ip(r), r.shape[0], _dp(out), nthreads)
+    return out
+
+
+def adjoint_voxels(g: dict, sino: np.ndarray, voxels: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """A^T sino at flat voxel indices (k*ny + j)*nx + i (gather form)."""
+    lib = _load()
+    G = _Geom(g)
+    y = np.ascontiguousarray(sino, dtype=np.float64)
+    v = np.ascontiguousarray(voxels, dtype=np.int64)
+    out = np.zeros(v.shape[0], dtype=np.float64)
+    rc = lib.orc_adjoint_voxels(G.ref, _dp(y), _ip(v), v.shape[0], _dp(out), nthreads)
+    if rc != 0:
+        raise RuntimeError("oracle adjoint_voxels: footprint window too small")
+    return out
+
+
+def sample_count(g: dict, nthreads: int = 0) -> int:
+    """Number of (ray, plane) samples with non-empty support."""
+    lib = _load()
+    G = _Geom(g)
+    return int(lib.orc_sample_count(G.ref, nthreads))
+
+
+def ray(g: dict, a: int, iu: int, iv: int):
+    """Source S and direction d = P - S of ray (a, iu, iv)."""
+    lib = _load()
+    G = _Geom(g)
+    S = np.zeros(3)
+    d = np.zeros(3)
+    lib.orc_ray(G.ref, a, iu, iv, _dp(S), _dp(d))
+    return S, d
+
+
+def weight(g: dict, a: int, iu: int, iv: int, i: int, j: int, k: int) -> float:
+    lib = _load()
+    G = _Geom(g)
+    return float(lib.orc_weight(G.ref, a, iu, iv, i, j, k))
+
+
+def chord_box(g: dict, a: int, iu: int, iv: int, lo, hi) -> float:
+    """Exact length of ray (a, iu, iv) inside the box [lo, hi] (slab clipping)."""
+    lib = _load()
+    G = _Geom(g)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    return float(lib.orc_chord_box(G.ref, a, iu, iv, _dp(lo), _dp(hi)))
+
+
+def siddon_dense(g: dict) -> np.ndarray:
+    """Dense [n_rays, n_voxels] matrix of exact ray-in-voxel-cube lengths."""
+    lib = _load()
+    G = _Geom(g)
+    nray = g["n_angles"] * g["nv"] * g["nu"]
+    nvox = g["nx"] * g["ny"] * g["nz"]
+    L = np.zeros((nray, nvox), dtype=np.float64)
+    lib.orc_siddon_dense(G.ref, _dp(L))
+    return L
+
+
+def interp_integral(g: dict, vol: np.ndarray, a: int, iu: int, iv: int) -> float:
+    """Exact line integral of the zero-padded trilinear interpolant of vol."""
+    lib = _load()
+    G = _Geom(g)
+    x = np.ascontiguousarray(vol, dtype=np.float64)
+    return float(lib.orc_interp_integral(G.ref, _dp(x), a, iu, iv))
+
+
+def dense_matrix(g: dict) -> np.ndarray:
+    """A as a dense [n_rays, n_voxels] matrix: column v = A e_v."""
+    nvox = g["nx"] * g["ny"] * g["nz"]
+    nray = g["n_angles"] * g["nv"] * g["nu"]
+    A = np.zeros((nray, nvox))
+    e = np.zeros(nvox)
+    for v in range(nvox):
+        e[v] = 1.0
+        A[:, v] = forward(g, e.reshape(vol_shape(g)), nthreads=1).ravel()
+        e[v] = 0.0
+    return A
+
+
+def cgls(g: dict, y: np.ndarray, iters: int, x0=None, callback=None) -> np.ndarray:
+    """Conjugate gradients on the normal equations A^T A x = A^T y (FP64).
+
+    Unregularised least squares started at x0 (default 0), the classical
+    CGLS recursion (Hestenes-Stiefel): q = A p, alpha = |s|^2/|q|^2,
+    x += alpha p, r -= alpha q, s = A^T r, beta = |s_new|^2/|s|^2,
+    p = s_new + beta p.
+    """
+    x = np.zeros(vol_shape(g)) if x0 is None else np.array(x0, dtype=np.float64)
+    r = np.asarray(y, dtype=np.float64) - forward(g, x)
+    s = adjoint(g, r)
+    p = s.copy()
+    gamma = float(np.vdot(s, s))
+    for it in range(iters):
+        if gamma == 0.0:
+            break
+        q = forward(g, p)
+        qq = float(np.vdot(q, q))
+        if qq == 0.0:
+            break
+        alpha = gamma / qq
+        x += alpha * p
+        r -= alpha * q
+        s = adjoint(g, r)
+        gamma_new = float(np.vdot(s, s))
+        p = s + (gamma_new / gamma) * p
+        gamma = gamma_new
+        if callback is not None:
+            callback(it + 1, x)
+    return x
+
+
+def opnorm(g: dict, iters: int = 50, seed: int = 0) -> float:
+    """||A||_2 by power iteration on A^T A (FP64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.standard_normal(vol_shape(g))
+    lam = 0.0
+    for _ in range(iters):
+        x /= np.linalg.norm(x)
+        z = adjoint(g, forward(g, x))
+        lam = float(np.vdot(x, z))
+        x = z
+    return float(np.sqrt(lam))
+
+
+def landweber(g: dict, y: np.ndarray, iters: int, omega: float, x0=None) -> np.ndarray:
+    """x <- x - omega * A^T (A x - y): the Landweber term of Alg. 1 as a solver."""
+    x = np.zeros(vol_shape(g)) if x0 is None else np.array(x0, dtype=np.float64)
+    for _ in range(iters):
+        x -= omega * adjoint(g, forward(g, x) - y)
+    return x
