@@ -1,0 +1,158 @@
+/*
+ * cbct.h -- C ABI of libcbct.so: the circular-orbit cone-beam projector pair
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Operators (arXiv 2512.21180, Sec. 2.2, definition of the cone-beam
+ * transform and of the backprojection as its adjoint; Alg. 1 applies both to
+ * multi-channel stacks and at several resolutions):
+ *
+ *   A   (forward projector)  line integrals of a voxel volume along the rays
+ *                            from the source to every detector pixel;
+ *   A^T (adjoint)            the exact Euclidean transpose of A, computed as
+ *                            a gather (every voxel written once, no atomics).
+ *
+ * Geometry (Sec. 2.2): isocenter at the origin, rotation axis z.  For source
+ * angle th the source is S = sid (cos th, sin th, 0); the panel is the plane
+ * at distance sdd from the source, perpendicular to the central ray, with
+ * columns along e_u = (-sin th, cos th, 0) (the direction of source motion)
+ * and rows along +z; its centre sits at -(sdd - sid)(cos th, sin th, 0) +
+ * off_u e_u + off_v e_z.  Pixel (iu, iv) is centred (iu - (nu-1)/2) du along
+ * e_u and (iv - (nv-1)/2) dv along z from the panel centre.  Voxel (i,j,k) is
+ * centred at origin + ((i-(nx-1)/2) vx, (j-(ny-1)/2) vy, (k-(nz-1)/2) vz).
+ *
+ * Discretisation: a ray whose direction d has |d_x| >= |d_y| is sampled on
+ * every voxel-centre plane x = const (else on the planes y = const); each
+ * sample is the bilinear interpolant, in the two remaining axes, of the
+ * zero-padded volume on that plane; the ray value is the sum of its samples
+ * times vox_major |d| / |d_major|, the ray length per plane spacing.
+ * Attenuation in mm^-1 gives dimensionless line integrals.
+ *
+ * Layouts (all dense, C order):
+ *   volume    [C][nz][ny][nx]          x fastest
+ *   sinogram  [C][n_angles][nv][nu]    u fastest
+ * where C = n_channels; all channels share the geometry.
+ *
+ * Ownership: every data pointer is a device pointer owned by the caller; the
+ * library never frees or keeps it after the call returns.  A geometry handle
+ * owns its device tables and is immutable after creation; one handle may be
+ * used from several streams at once.
+ *
+ * Execution: compute calls only enqueue work on `stream` (a hipStream_t; NULL
+ * selects the null stream) and return; outputs are overwritten, never
+ * accumulated.  Results are bitwise reproducible run to run and identical
+ * between the single-case and the batched entry points.
+ *
+ * Errors: every call returns a status; nothing aborts.  Validation happens on
+ * the host before any device work is enqueued, so a failed call leaves the
+ * outputs untouched.
+ */
+#ifndef CBCT_H
+#define CBCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage type of a volume or sinogram buffer.  Arithmetic is always FP32;
+ * BF16/FP16 buffers are widened on load and rounded to nearest-even on
+ * store. */
+typedef enum { CBCT_F32 = 0, CBCT_BF16 = 1, CBCT_F16 = 2 } cbct_dtype;
+
+typedef enum {
+    CBCT_OK = 0,
+    CBCT_E_NULL = -1,   /* a required pointer is NULL */
+    CBCT_E_GEOM = -2,   /* geometry rejected (see cbct_geom_create) */
+    CBCT_E_DTYPE = -3,  /* unknown storage type */
+    CBCT_E_SHAPE = -4,  /* sizes out of range (channels, batch count, index range) */
+    CBCT_E_HIP = -5,    /* a HIP runtime call failed; see cbct_last_hip_error */
+    CBCT_E_ALLOC = -6,  /* host or device allocation failed */
+    CBCT_E_ARG = -7     /* any other invalid argument */
+} cbct_status;
+
+/* Acquisition and volume geometry (Sec. 2.2).  Distances in mm, angles in
+ * radians. */
+typedef struct {
+    double sid_mm;              /* source to isocenter, > 0 (paper: 1000) */
+    double sdd_mm;              /* source to panel, > sid_mm (paper: 1000 + 536) */
+    int n_angles;               /* number of source positions, > 0 */
+    const double *angles_rad;   /* host array of n_angles angles, or NULL for
+                                   2 pi a / n_angles (a = 0..n_angles-1); copied */
+    int nu, nv;                 /* panel columns (along e_u) and rows (along z) */
+    double du_mm, dv_mm;        /* pixel pitch, > 0 */
+    double off_u_mm, off_v_mm;  /* panel-centre offset along e_u and z (paper: 115 lateral) */
+    int nx, ny, nz;             /* voxel counts, > 0 */
+    double vx_mm, vy_mm, vz_mm; /* voxel pitch, > 0 */
+    double origin_mm[3];        /* volume centre relative to the isocenter */
+} cbct_geom_desc;
+
+typedef struct cbct_geom cbct_geom;   /* opaque, immutable after creation */
+
+/*
+ * Validate `desc`, build the per-angle and per-column tables in FP64 on the
+ * host, round them to FP32 and upload them to the current HIP device.
+ * CBCT_E_GEOM is returned when: a size or pitch is not positive, sdd <= sid,
+ * an angle is not finite, the volume's support (the voxel box widened by one
+ * voxel in x and y) is not strictly inside the cylinder of radius
+ * min(sid, sdd - sid) about z (so some sample would not lie strictly between
+ * source and panel), a ray is steeper in z than in x and y
+ * (|d_z| >= max(|d_x|, |d_y|)), the columns of one angle change sampling axis
+ * more than once, or a size exceeds 2^31 elements.  On success *out
+ * receives a handle to release with cbct_geom_destroy.
+ */
+cbct_status cbct_geom_create(const cbct_geom_desc *desc, cbct_geom **out);
+
+/* Release a handle and its device tables (NULL is accepted).  The caller
+ * must ensure no enqueued work still uses it. */
+cbct_status cbct_geom_destroy(cbct_geom *g);
+
+/* Number of samples one application of A (or A^T) performs: the (ray, plane)
+ * pairs whose bilinear support meets the volume.  This is the unit of the
+ * Gsamples/s throughput figures.  Computed on the host in FP64, once. */
+cbct_status cbct_sample_count(const cbct_geom *g, uint64_t *samples);
+
+/* Sizes of one channel: voxels (nx*ny*nz) and sinogram elements
+ * (n_angles*nv*nu). */
+cbct_status cbct_geom_sizes(const cbct_geom *g, uint64_t *n_vox, uint64_t *n_sino);
+
+/*
+ * sino = A vol for n_channels >= 1 stacked channels.  vol (storage vt) is
+ * [C][nz][ny][nx]; sino (storage st) is [C][n_angles][nv][nu].
+ */
+cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,
+                         void *sino, cbct_dtype st, int n_channels, void *stream);
+
+/*
+ * vol = A^T sino for n_channels >= 1 stacked channels (layouts as above).
+ * The weights are the ones cbct_forward applies, so the two are transposes
+ * up to FP32 rounding of the sums.
+ */
+cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
+                         void *vol, cbct_dtype vt, int n_channels, void *stream);
+
+/*
+ * Batched forward over n >= 1 independent single-channel cases, each with
+ * its own geometry handle and buffers (host arrays of n handles and n device
+ * pointers), in one persistent launch.  Results are bitwise identical to n
+ * separate cbct_forward calls.
+ */
+cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,
+                               void *const *sinos, cbct_dtype vt, cbct_dtype st, void *stream);
+
+/* Batched adjoint, the counterpart of cbct_batch_forward. */
+cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, const void *const *sinos,
+                               void *const *vols, cbct_dtype st, cbct_dtype vt, void *stream);
+
+/* Static, human-readable description of a status code. */
+const char *cbct_error_string(cbct_status e);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char *cbct_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBCT_H */

@@ -1,0 +1,238 @@
+"""ctypes binding of libcbct.so: argument marshalling only.
+
+Every computation runs in the library's HIP kernels; PyTorch tensors serve as
+device buffers and PyTorch's current stream as the launch stream.  There is
+no fallback: if the library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcbct.so")
+
+F32, BF16, F16 = 0, 1, 2
+_TORCH2CODE = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+
+
+class CbctError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.cbct_error_string(status).decode()
+        if status == -5:
+            msg += ": " + _lib.cbct_last_hip_error().decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("sid_mm", ctypes.c_double), ("sdd_mm", ctypes.c_double),
+        ("n_angles", ctypes.c_int), ("angles_rad", ctypes.POINTER(ctypes.c_double)),
+        ("nu", ctypes.c_int), ("nv", ctypes.c_int),
+        ("du_mm", ctypes.c_double), ("dv_mm", ctypes.c_double),
+        ("off_u_mm", ctypes.c_double), ("off_v_mm", ctypes.c_double),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("vx_mm", ctypes.c_double), ("vy_mm", ctypes.c_double), ("vz_mm", ctypes.c_double),
+        ("origin_mm", ctypes.c_double * 3),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, u64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
+    lib.cbct_geom_create.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+    lib.cbct_geom_destroy.argtypes = [vp]
+    lib.cbct_sample_count.argtypes = [vp, u64p]
+    lib.cbct_geom_sizes.argtypes = [vp, u64p, u64p]
+    lib.cbct_forward.argtypes = [vp, vp, i32, vp, i32, i32, vp]
+    lib.cbct_adjoint.argtypes = [vp, vp, i32, vp, i32, i32, vp]
+    lib.cbct_batch_forward.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), i32, i32, vp]
+    lib.cbct_batch_adjoint.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), i32, i32, vp]
+    lib.cbct_error_string.argtypes = [i32]
+    lib.cbct_error_string.restype = ctypes.c_char_p
+    lib.cbct_last_hip_error.argtypes = []
+    lib.cbct_last_hip_error.restype = ctypes.c_char_p
+    for name in ("cbct_geom_create", "cbct_geom_destroy", "cbct_sample_count", "cbct_geom_sizes",
+                 "cbct_forward", "cbct_adjoint", "cbct_batch_forward", "cbct_batch_adjoint"):
+        getattr(lib, name).restype = i32
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise CbctError(status, where)
+
+
+def make_desc(g: dict):
+    """C descriptor for a geometry dict; returns (desc, keep-alive angle array)."""
+    import numpy as np
+    ang = g.get("angles")
+    arr = None
+    ptr = None
+    if ang is not None:
+        arr = np.ascontiguousarray(np.asarray(ang, dtype=np.float64))
+        ptr = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    o = g.get("origin", (0.0, 0.0, 0.0))
+    d = Desc(float(g["sid"]), float(g["sdd"]), int(g["n_angles"]), ptr,
+             int(g["nu"]), int(g["nv"]), float(g["du"]), float(g["dv"]),
+             float(g.get("off_u", 0.0)), float(g.get("off_v", 0.0)),
+             int(g["nx"]), int(g["ny"]), int(g["nz"]),
+             float(g["vx"]), float(g["vy"]), float(g["vz"]),
+             (ctypes.c_double * 3)(*[float(v) for v in o]))
+    return d, arr
+
+
+class Geometry:
+    """A validated geometry with its device tables (on the current device)."""
+
+    def __init__(self, g: dict, device=None):
+        self.params = dict(g)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        desc, keep = make_desc(g)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.cbct_geom_create(ctypes.byref(desc), ctypes.byref(h)), "cbct_geom_create")
+        del keep
+        self._h = h
+        self.vol_shape = (g["nz"], g["ny"], g["nx"])
+        self.sino_shape = (g["n_angles"], g["nv"], g["nu"])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sample_count(self) -> int:
+        s = ctypes.c_uint64()
+        _check(_lib.cbct_sample_count(self._h, ctypes.byref(s)), "cbct_sample_count")
+        return int(s.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.cbct_geom_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _code(t: torch.Tensor) -> int:
+    try:
+        return _TORCH2CODE[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype}") from None
+
+
+def _stream(dev) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _prep(t: torch.Tensor, geom: Geometry, shape, what: str):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a CUDA (HIP) tensor")
+    if t.device != geom.device:
+        raise ValueError(f"{what} is on {t.device}, geometry on {geom.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if tuple(t.shape[-3:]) != tuple(shape):
+        raise ValueError(f"{what} has shape {tuple(t.shape)}, expected [..., {shape}]")
+    return t.numel() // (shape[0] * shape[1] * shape[2])
+
+
+def forward(geom: Geometry, vol: torch.Tensor, out: torch.Tensor | None = None,
+            out_dtype: torch.dtype | None = None) -> torch.Tensor:
+    """Sinogram(s) A vol.  vol: [..., nz, ny, nx] (channels flattened)."""
+    C = _prep(vol, geom, geom.vol_shape, "vol")
+    if out is None:
+        out = torch.empty(tuple(vol.shape[:-3]) + geom.sino_shape, device=vol.device,
+                          dtype=out_dtype or vol.dtype)
+    else:
+        if _prep(out, geom, geom.sino_shape, "out") != C:
+            raise ValueError("channel count of out does not match vol")
+    with torch.cuda.device(geom.device):
+        _check(_lib.cbct_forward(geom.handle, ctypes.c_void_p(vol.data_ptr()), _code(vol),
+                                 ctypes.c_void_p(out.data_ptr()), _code(out), C,
+                                 _stream(geom.device)), "cbct_forward")
+    return out
+
+
+def adjoint(geom: Geometry, sino: torch.Tensor, out: torch.Tensor | None = None,
+            out_dtype: torch.dtype | None = None) -> torch.Tensor:
+    """Volume(s) A^T sino.  sino: [..., n_angles, nv, nu]."""
+    C = _prep(sino, geom, geom.sino_shape, "sino")
+    if out is None:
+        out = torch.empty(tuple(sino.shape[:-3]) + geom.vol_shape, device=sino.device,
+                          dtype=out_dtype or sino.dtype)
+    else:
+        if _prep(out, geom, geom.vol_shape, "out") != C:
+            raise ValueError("channel count of out does not match sino")
+    with torch.cuda.device(geom.device):
+        _check(_lib.cbct_adjoint(geom.handle, ctypes.c_void_p(sino.data_ptr()), _code(sino),
+                                 ctypes.c_void_p(out.data_ptr()), _code(out), C,
+                                 _stream(geom.device)), "cbct_adjoint")
+    return out
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[ctypes.c_void_p(t.data_ptr()) for t in ts])
+
+
+def batch_forward(geoms, vols, outs=None, out_dtype=None):
+    """One launch: sinos[i] = A_i vols[i] for heterogeneous single-channel cases."""
+    n = len(geoms)
+    assert len(vols) == n and n > 0
+    for g, v in zip(geoms, vols):
+        if _prep(v, g, g.vol_shape, "vol") != 1:
+            raise ValueError("batch entries are single-channel")
+    if outs is None:
+        outs = [torch.empty(g.sino_shape, device=v.device, dtype=out_dtype or v.dtype)
+                for g, v in zip(geoms, vols)]
+    vt, st = _code(vols[0]), _code(outs[0])
+    if any(_code(v) != vt for v in vols) or any(_code(o) != st for o in outs):
+        raise TypeError("batch entries must share storage types")
+    for g, o in zip(geoms, outs):
+        _prep(o, g, g.sino_shape, "out")
+    hs = (ctypes.c_void_p * n)(*[g.handle for g in geoms])
+    with torch.cuda.device(geoms[0].device):
+        _check(_lib.cbct_batch_forward(n, hs, _ptrs(vols), _ptrs(outs), vt, st,
+                                       _stream(geoms[0].device)), "cbct_batch_forward")
+    return outs
+
+
+def batch_adjoint(geoms, sinos, outs=None, out_dtype=None):
+    """One launch: vols[i] = A_i^T sinos[i] for heterogeneous single-channel cases."""
+    n = len(geoms)
+    assert len(sinos) == n and n > 0
+    for g, s in zip(geoms, sinos):
+        if _prep(s, g, g.sino_shape, "sino") != 1:
+            raise ValueError("batch entries are single-channel")
+    if outs is None:
+        outs = [torch.empty(g.vol_shape, device=s.device, dtype=out_dtype or s.dtype)
+                for g, s in zip(geoms, sinos)]
+    st, vt = _code(sinos[0]), _code(outs[0])
+    if any(_code(s) != st for s in sinos) or any(_code(o) != vt for o in outs):
+        raise TypeError("batch entries must share storage types")
+    for g, o in zip(geoms, outs):
+        _prep(o, g, g.vol_shape, "out")
+    hs = (ctypes.c_void_p * n)(*[g.handle for g in geoms])
+    with torch.cuda.device(geoms[0].device):
+        _check(_lib.cbct_batch_adjoint(n, hs, _ptrs(sinos), _ptrs(outs), st, vt,
+                                       _stream(geoms[0].device)), "cbct_batch_adjoint")
+    return outs

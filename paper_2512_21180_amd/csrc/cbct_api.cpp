@@ -1,0 +1,112 @@
+// C-ABI compute entry points of libcbct.so: argument validation and kernel
+// launches for the projector pair (arXiv 2512.21180, Sec. 2.2; multi-channel
+// and multi-resolution use as in Alg. 1).
+#include <hip/hip_runtime.h>
+
+#include "cbct_internal.h"
+
+using namespace cbct;
+
+static bool dtype_ok(cbct_dtype t) { return t == CBCT_F32 || t == CBCT_BF16 || t == CBCT_F16; }
+
+static cbct_status check_device(const cbct_geom *g)
+{
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        return CBCT_E_HIP;
+    }
+    if (cur != g->device) {
+        set_hip_error(hipErrorInvalidDevice);
+        return CBCT_E_HIP;
+    }
+    return CBCT_OK;
+}
+
+static cbct_status finish(hipError_t e)
+{
+    if (e == hipSuccess)
+        return CBCT_OK;
+    set_hip_error(e);
+    return e == hipErrorInvalidValue ? CBCT_E_DTYPE : CBCT_E_HIP;
+}
+
+extern "C" cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,
+                                    void *sino, cbct_dtype st, int n_channels, void *stream)
+{
+    if (!g || !vol || !sino)
+        return CBCT_E_NULL;
+    if (!dtype_ok(vt) || !dtype_ok(st))
+        return CBCT_E_DTYPE;
+    if (n_channels < 1 || (int64_t)n_channels * g->desc.n_angles > 65535)
+        return CBCT_E_SHAPE;
+    cbct_status s = check_device(g);
+    if (s != CBCT_OK)
+        return s;
+    return finish(launch_forward(g->dev, vol, vt, sino, st, n_channels, (hipStream_t)stream));
+}
+
+extern "C" cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
+                                    void *vol, cbct_dtype vt, int n_channels, void *stream)
+{
+    if (!g || !vol || !sino)
+        return CBCT_E_NULL;
+    if (!dtype_ok(vt) || !dtype_ok(st))
+        return CBCT_E_DTYPE;
+    if (n_channels < 1 || n_channels > 65535)
+        return CBCT_E_SHAPE;
+    cbct_status s = check_device(g);
+    if (s != CBCT_OK)
+        return s;
+    return finish(launch_adjoint(g->dev, sino, st, vol, vt, n_channels, (hipStream_t)stream));
+}
+
+static cbct_status check_batch(int n, const cbct_geom *const *g, const void *const *a,
+                               const void *const *b, cbct_dtype t1, cbct_dtype t2)
+{
+    if (n < 1)
+        return CBCT_E_SHAPE;
+    if (!g || !a || !b)
+        return CBCT_E_NULL;
+    if (!dtype_ok(t1) || !dtype_ok(t2))
+        return CBCT_E_DTYPE;
+    for (int i = 0; i < n; ++i) {
+        if (!g[i] || !a[i] || !b[i])
+            return CBCT_E_NULL;
+        cbct_status s = check_device(g[i]);
+        if (s != CBCT_OK)
+            return s;
+    }
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,
+                                          void *const *sinos, cbct_dtype vt, cbct_dtype st,
+                                          void *stream)
+{
+    cbct_status s = check_batch(n, g, vols, (const void *const *)sinos, vt, st);
+    if (s != CBCT_OK)
+        return s;
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = launch_forward(g[i]->dev, vols[i], vt, sinos[i], st, 1, (hipStream_t)stream);
+        if (e != hipSuccess)
+            return finish(e);
+    }
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, const void *const *sinos,
+                                          void *const *vols, cbct_dtype st, cbct_dtype vt,
+                                          void *stream)
+{
+    cbct_status s = check_batch(n, g, sinos, (const void *const *)vols, st, vt);
+    if (s != CBCT_OK)
+        return s;
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = launch_adjoint(g[i]->dev, sinos[i], st, vols[i], vt, 1, (hipStream_t)stream);
+        if (e != hipSuccess)
+            return finish(e);
+    }
+    return CBCT_OK;
+}
