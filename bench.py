@@ -1,0 +1,151 @@
+"""Benchmark of the cone-beam projector pair on one MI355X.
+
+One step = one forward projection A and one adjoint A^T of the clinical-size
+case (256^3 volume at 2 mm, 360 angles over 2 pi, 512^2 panel at 0.8 mm with a
+115 mm lateral offset, source-isocenter 1000 mm, source-panel 1536 mm) in
+FP32, on a seeded synthetic phantom already resident in HBM.  Throughput is
+(S_A + S_AT) / time in Gsamples/s, where S is the library's sample count
+(ray-plane pairs with non-empty support; A^T applies the same samples).
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
+GPU only.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "A+A^T Gsamples/s at 256³×360×512²; recon s to fixed PSNR, learned vs CGLS"
+
+# Algorithmic FP32 VALU lane-operations per sample: two FMAs for the in-plane
+# and z coordinates, two floors and two fraction subtractions, three linear
+# interpolations (subtract + FMA each) and one accumulation.
+OPS_PER_SAMPLE = 14
+# Non-packed FP32 VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def cpu_baseline(g, n_angles=72):
+    """The FP64 oracle on the same geometry restricted to n_angles of its
+    angles (every n/n_angles-th), forward then adjoint."""
+    import numpy as np
+    from oracle import oracle as orc
+    from paper_2512_21180_amd import workloads as W
+
+    all_ang = orc.angles_of(g)
+    step = max(1, g["n_angles"] // n_angles)
+    sub = dict(g, n_angles=len(all_ang[::step][:n_angles]), angles=all_ang[::step][:n_angles])
+    x, _, _ = W.phantom_c2(g, 2025)
+    S = orc.sample_count(sub)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    y = orc.forward(sub, x, nthreads=threads)
+    t1 = time.perf_counter()
+    orc.adjoint(sub, y, nthreads=threads)
+    t2 = time.perf_counter()
+    del np
+    return {
+        "value": round(2 * S / (t2 - t0) / 1e9, 4),
+        "unit": "Gsamples/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"FP64 oracle A then scatter A^T on the same case restricted to {sub['n_angles']} "
+                  f"of its {g['n_angles']} angles ({S} samples each); forward {t1 - t0:.1f} s, "
+                  f"adjoint {t2 - t1:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on a single GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_21180_amd import cbct
+    from paper_2512_21180_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    g = W.C2
+    geo = cbct.Geometry(g)
+    S = geo.sample_count()
+    x_host, _, _ = W.phantom_c2(g, 2025)
+    x = torch.tensor(x_host, dtype=torch.float32, device="cuda")
+    y = torch.empty(geo.sino_shape, dtype=torch.float32, device="cuda")
+    xb = torch.empty(geo.vol_shape, dtype=torch.float32, device="cuda")
+
+    for _ in range(args.warmup):
+        cbct.forward(geo, x, out=y)
+        cbct.adjoint(geo, y, out=xb)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record()
+        cbct.forward(geo, x, out=y)
+        ev[k][1].record()
+        cbct.adjoint(geo, y, out=xb)
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    tA = sum(e[0].elapsed_time(e[1]) for e in ev) / K * 1e-3
+    tAT = sum(e[1].elapsed_time(e[2]) for e in ev) / K * 1e-3
+    value = 2 * S * K / wall / 1e9
+    dom, tdom = ("adjoint", tAT) if tAT >= tA else ("forward", tA)
+    achieved = OPS_PER_SAMPLE * S / tdom / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "256^3 @2 mm volume, 360 angles over 2 pi, 512^2 panel @0.8 mm, "
+                        "115 mm lateral offset, sid 1000 / sdd 1536 mm; 50-ellipsoid phantom "
+                        "in a 300 mm body cylinder; FP32 A + A^T",
+            "samples_per_operator": S,
+        },
+        "kernels": {
+            "forward_ms": round(tA * 1e3, 3),
+            "adjoint_ms": round(tAT * 1e3, 3),
+            "forward_gsamples_s": round(S / tA / 1e9, 2),
+            "adjoint_gsamples_s": round(S / tAT / 1e9, 2),
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": round(achieved, 3),
+            "peak": round(VALU_PEAK_TOPS, 3),
+            "unit": "TOP/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -145,6 +145,29 @@ cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *con
 cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, const void *const *sinos,
                                void *const *vols, cbct_dtype st, cbct_dtype vt, void *stream);
 
+/* Host-only handle: the same validation, tables, plans and sample count as
+ * cbct_geom_create, without touching any device.  Compute calls on it return
+ * CBCT_E_ARG.  For inspection and for testing host logic on machines without
+ * a GPU. */
+cbct_status cbct_geom_create_host(const cbct_geom_desc *desc, cbct_geom **out);
+
+/* Copy a host table of a handle into dst (cap bytes); *bytes receives its
+ * size (dst may be NULL to query it).  which: 0 per-(angle, column) records
+ * {pb, ps, t0, tau, dsf, n2, 0, 0} (float32 x 8, angle-major); 1 per-angle
+ * records {cos, sin (float32), x_lo, x_hi (int32)}; 2 per-row {V/vz, V^2}
+ * (float32 x 2); 3 forward tiles {angle, axis, u0, n_u, v0, n_v, p_lo, p_hi}
+ * (int32 x 8); 4 the scalar block {n_angles, nu, nv, nx, ny, nz (int32), Kb,
+ * vx, vy, vz, ox, oy, oz, sid, sdd, du, dv, off_u, off_v, cu, cv, rv0, rvs
+ * (float32)}. */
+cbct_status cbct_geom_table(const cbct_geom *g, int which, void *dst, size_t cap, size_t *bytes);
+
+/* Diagnostics: the launch plan chosen for a geometry.  Fills up to n of
+ * {forward tiled (1/0), rays per thread, box in-plane, box z, tile count,
+ *  adjoint bricked (1/0), window columns, window rows, LDS row stride,
+ *  max row taps}.  A 0 in either flag means that operator runs the
+ * one-thread-per-output kernels. */
+cbct_status cbct_geom_plan_info(const cbct_geom *g, int *info, int n);
+
 /* Static, human-readable description of a status code. */
 const char *cbct_error_string(cbct_status e);
 

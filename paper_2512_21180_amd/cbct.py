@@ -55,12 +55,24 @@ def _load():
                                        ctypes.POINTER(vp), i32, i32, vp]
     lib.cbct_batch_adjoint.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                        ctypes.POINTER(vp), i32, i32, vp]
+    lib.cbct_geom_plan_info.argtypes = [vp, ctypes.POINTER(i32), i32]
+    lib.cbct_geom_create_host.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+    lib.cbct_geom_table.argtypes = [vp, i32, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    sz, dp = ctypes.c_size_t, ctypes.c_double
+    lib.cbct_dot_workspace.argtypes = [sz]
+    lib.cbct_dot_workspace.restype = sz
+    lib.cbct_dot.argtypes = [sz, vp, vp, vp, vp, vp]
+    lib.cbct_axpy_ratio.argtypes = [sz, vp, vp, vp, vp, dp, vp]
+    lib.cbct_xpay_ratio.argtypes = [sz, vp, vp, vp, vp, vp]
+    lib.cbct_axpby.argtypes = [sz, vp, ctypes.c_float, vp, ctypes.c_float, vp, vp]
     lib.cbct_error_string.argtypes = [i32]
     lib.cbct_error_string.restype = ctypes.c_char_p
     lib.cbct_last_hip_error.argtypes = []
     lib.cbct_last_hip_error.restype = ctypes.c_char_p
     for name in ("cbct_geom_create", "cbct_geom_destroy", "cbct_sample_count", "cbct_geom_sizes",
-                 "cbct_forward", "cbct_adjoint", "cbct_batch_forward", "cbct_batch_adjoint"):
+                 "cbct_forward", "cbct_adjoint", "cbct_batch_forward", "cbct_batch_adjoint",
+                 "cbct_geom_plan_info", "cbct_geom_create_host", "cbct_geom_table",
+                 "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -120,6 +132,13 @@ class Geometry:
         s = ctypes.c_uint64()
         _check(_lib.cbct_sample_count(self._h, ctypes.byref(s)), "cbct_sample_count")
         return int(s.value)
+
+    def plan_info(self) -> dict:
+        v = (ctypes.c_int * 10)()
+        _check(_lib.cbct_geom_plan_info(self._h, v, 10), "cbct_geom_plan_info")
+        keys = ("fwd_tiled", "rays_per_thread", "box_q", "box_k", "tiles",
+                "adj_bricked", "win_cols", "win_rows", "lds_stride", "nt_max")
+        return dict(zip(keys, list(v)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -236,3 +255,58 @@ def batch_adjoint(geoms, sinos, outs=None, out_dtype=None):
         _check(_lib.cbct_batch_adjoint(n, hs, _ptrs(sinos), _ptrs(outs), st, vt,
                                        _stream(geoms[0].device)), "cbct_batch_adjoint")
     return outs
+
+
+# ---- BLAS-1 (cbct_solve.h) -------------------------------------------------
+
+def _f32(t: torch.Tensor, what: str):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous float32 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64cell(t: torch.Tensor, what: str):
+    if not (t.is_cuda and t.dtype == torch.float64 and t.numel() >= 1):
+        raise ValueError(f"{what} must be a float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def dot_workspace(n: int, device) -> torch.Tensor:
+    return torch.empty(int(_lib.cbct_dot_workspace(n)), dtype=torch.float64, device=device)
+
+
+def dot(a: torch.Tensor, b: torch.Tensor, ws: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """out[0] = sum(a*b) in FP64, deterministic; a, b float32; out float64 cell."""
+    if a.numel() != b.numel():
+        raise ValueError("size mismatch")
+    _check(_lib.cbct_dot(a.numel(), _f32(a, "a"), _f32(b, "b"), _f64cell(ws, "ws"),
+                         _f64cell(out, "out"), _stream(a.device)), "cbct_dot")
+    return out
+
+
+def axpy_ratio(y, x, num, den, sign=1.0):
+    """y += sign * (num/den) * x with device FP64 scalars."""
+    if y.numel() != x.numel():
+        raise ValueError("size mismatch")
+    _check(_lib.cbct_axpy_ratio(y.numel(), _f32(y, "y"), _f32(x, "x"), _f64cell(num, "num"),
+                                _f64cell(den, "den"), float(sign), _stream(y.device)),
+           "cbct_axpy_ratio")
+    return y
+
+
+def xpay_ratio(y, x, num, den):
+    """y = x + (num/den) * y with device FP64 scalars."""
+    if y.numel() != x.numel():
+        raise ValueError("size mismatch")
+    _check(_lib.cbct_xpay_ratio(y.numel(), _f32(y, "y"), _f32(x, "x"), _f64cell(num, "num"),
+                                _f64cell(den, "den"), _stream(y.device)), "cbct_xpay_ratio")
+    return y
+
+
+def axpby(z, alpha, x, beta, y):
+    """z = alpha*x + beta*y (z may alias x or y)."""
+    if not (z.numel() == x.numel() == y.numel()):
+        raise ValueError("size mismatch")
+    _check(_lib.cbct_axpby(z.numel(), _f32(z, "z"), float(alpha), _f32(x, "x"), float(beta),
+                           _f32(y, "y"), _stream(z.device)), "cbct_axpby")
+    return z

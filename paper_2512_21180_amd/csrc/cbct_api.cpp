@@ -5,12 +5,34 @@
 
 #include "cbct_internal.h"
 
+namespace cbct {
+
+hipError_t launch_forward(const cbct_geom *g, const void *vol, cbct_dtype vt, void *sino,
+                          cbct_dtype st, int channels, hipStream_t s)
+{
+    if (g->fwd.ok)
+        return launch_forward_tiled(g->dev, g->fwd, vol, vt, sino, st, channels, s);
+    return launch_forward_simple(g->dev, vol, vt, sino, st, channels, s);
+}
+
+hipError_t launch_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st, void *vol,
+                          cbct_dtype vt, int channels, hipStream_t s)
+{
+    if (g->adj.ok)
+        return launch_adjoint_brick(g->dev, g->adj, sino, st, vol, vt, channels, s);
+    return launch_adjoint_simple(g->dev, sino, st, vol, vt, channels, s);
+}
+
+}  // namespace cbct
+
 using namespace cbct;
 
 static bool dtype_ok(cbct_dtype t) { return t == CBCT_F32 || t == CBCT_BF16 || t == CBCT_F16; }
 
 static cbct_status check_device(const cbct_geom *g)
 {
+    if (!g->dev_block)
+        return CBCT_E_ARG;   // host-only handle
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) {
@@ -39,12 +61,13 @@ extern "C" cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dt
         return CBCT_E_NULL;
     if (!dtype_ok(vt) || !dtype_ok(st))
         return CBCT_E_DTYPE;
-    if (n_channels < 1 || (int64_t)n_channels * g->desc.n_angles > 65535)
+    if (n_channels < 1 || n_channels > 65535 ||
+        (!g->fwd.ok && (int64_t)n_channels * g->desc.n_angles > 65535))
         return CBCT_E_SHAPE;
     cbct_status s = check_device(g);
     if (s != CBCT_OK)
         return s;
-    return finish(launch_forward(g->dev, vol, vt, sino, st, n_channels, (hipStream_t)stream));
+    return finish(launch_forward(g, vol, vt, sino, st, n_channels, (hipStream_t)stream));
 }
 
 extern "C" cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
@@ -59,7 +82,7 @@ extern "C" cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_d
     cbct_status s = check_device(g);
     if (s != CBCT_OK)
         return s;
-    return finish(launch_adjoint(g->dev, sino, st, vol, vt, n_channels, (hipStream_t)stream));
+    return finish(launch_adjoint(g, sino, st, vol, vt, n_channels, (hipStream_t)stream));
 }
 
 static cbct_status check_batch(int n, const cbct_geom *const *g, const void *const *a,
@@ -89,7 +112,7 @@ extern "C" cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, cons
     if (s != CBCT_OK)
         return s;
     for (int i = 0; i < n; ++i) {
-        hipError_t e = launch_forward(g[i]->dev, vols[i], vt, sinos[i], st, 1, (hipStream_t)stream);
+        hipError_t e = launch_forward(g[i], vols[i], vt, sinos[i], st, 1, (hipStream_t)stream);
         if (e != hipSuccess)
             return finish(e);
     }
@@ -104,9 +127,20 @@ extern "C" cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, cons
     if (s != CBCT_OK)
         return s;
     for (int i = 0; i < n; ++i) {
-        hipError_t e = launch_adjoint(g[i]->dev, sinos[i], st, vols[i], vt, 1, (hipStream_t)stream);
+        hipError_t e = launch_adjoint(g[i], sinos[i], st, vols[i], vt, 1, (hipStream_t)stream);
         if (e != hipSuccess)
             return finish(e);
     }
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_geom_plan_info(const cbct_geom *g, int *info, int n)
+{
+    if (!g || !info)
+        return CBCT_E_NULL;
+    int v[10] = {g->fwd.ok ? 1 : 0, g->fwd.R, g->fwd.BQ, g->fwd.BK, g->fwd.n_tiles,
+                 g->adj.ok ? 1 : 0, g->adj.W, g->adj.H, g->adj.WS, g->adj.NTmax};
+    for (int i = 0; i < n && i < 10; ++i)
+        info[i] = v[i];
     return CBCT_OK;
 }

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 
@@ -146,29 +147,19 @@ static cbct_status validate(const cbct_geom_desc &d, const std::vector<double> &
     return CBCT_OK;
 }
 
-// FP64 ray-family constants for column iu at angle index a.
+// FP32 table record of column iu at angle th.
 static void column_constants(const cbct_geom_desc &d, double th, int iu, ColRec *r, int *is_x)
 {
-    double c = std::cos(th), s = std::sin(th);
-    double Sx = d.sid_mm * c, Sy = d.sid_mm * s;
-    double dx, dy;
-    ray_xy(d, c, s, iu, &dx, &dy);
-    bool xm = std::fabs(dx) >= std::fabs(dy);
-    double dm = xm ? dx : dy, dq = xm ? dy : dx;
-    double Sm = xm ? Sx : Sy, Sq = xm ? Sy : Sx;
-    double vm = xm ? d.vx_mm : d.vy_mm, vq = xm ? d.vy_mm : d.vx_mm;
-    double om = xm ? d.origin_mm[0] : d.origin_mm[1], oq = xm ? d.origin_mm[1] : d.origin_mm[0];
-    int nm = xm ? d.nx : d.ny, nq = xm ? d.ny : d.nx;
-    double c0 = om - 0.5 * (nm - 1) * vm;          // centre of plane 0 along m
-    double t0 = (c0 - Sm) / dm, tau = vm / dm;
-    r->pb = (float)((Sq - oq + t0 * dq) / vq + 0.5 * (nq - 1));
-    r->ps = (float)(tau * dq / vq);
-    r->t0 = (float)t0;
-    r->tau = (float)tau;
-    r->dsf = (float)(vm / std::fabs(dm));
-    r->n2 = (float)(dx * dx + dy * dy);
+    Col64 k = col_consts64(d, std::cos(th), std::sin(th), iu);
+    double vm = k.xm ? d.vx_mm : d.vy_mm;
+    r->pb = (float)k.pb;
+    r->ps = (float)k.ps;
+    r->t0 = (float)k.t0;
+    r->tau = (float)k.tau;
+    r->dsf = (float)(vm / std::fabs(k.xm ? k.dx : k.dy));
+    r->n2 = (float)(k.dx * k.dx + k.dy * k.dy);
     r->pad0 = r->pad1 = 0.0f;
-    *is_x = xm;
+    *is_x = k.xm;
 }
 
 // Samples with non-empty support, in FP64 from the closed-form ray lines.
@@ -177,23 +168,12 @@ static uint64_t count_samples(const cbct_geom_desc &d, const std::vector<double>
     double Kb = 0.5 * (d.nz - 1) - d.origin_mm[2] / d.vz_mm;
     uint64_t total = 0;
     for (int a = 0; a < d.n_angles; ++a) {
-        double th = ang[a];
-        double c = std::cos(th), s = std::sin(th);
-        double Sx = d.sid_mm * c, Sy = d.sid_mm * s;
+        double c = std::cos(ang[a]), s = std::sin(ang[a]);
         for (int iu = 0; iu < d.nu; ++iu) {
-            double dx, dy;
-            ray_xy(d, c, s, iu, &dx, &dy);
-            bool xm = std::fabs(dx) >= std::fabs(dy);
-            double dm = xm ? dx : dy, dq = xm ? dy : dx;
-            double Sm = xm ? Sx : Sy, Sq = xm ? Sy : Sx;
-            double vm = xm ? d.vx_mm : d.vy_mm, vq = xm ? d.vy_mm : d.vx_mm;
-            double om = xm ? d.origin_mm[0] : d.origin_mm[1];
-            double oq = xm ? d.origin_mm[1] : d.origin_mm[0];
-            int nm = xm ? d.nx : d.ny, nq = xm ? d.ny : d.nx;
-            double t0 = (om - 0.5 * (nm - 1) * vm - Sm) / dm, tau = vm / dm;
-            double pb = (Sq - oq + t0 * dq) / vq + 0.5 * (nq - 1), ps = tau * dq / vq;
+            Col64 k = col_consts64(d, c, s, iu);
+            int nm = k.xm ? d.nx : d.ny, nq = k.xm ? d.ny : d.nx;
             int64_t lq, hq;
-            open_range(pb, ps, -1.0, (double)nq, &lq, &hq);
+            open_range(k.pb, k.ps, -1.0, (double)nq, &lq, &hq);
             lq = std::max<int64_t>(lq, 0);
             hq = std::min<int64_t>(hq, nm - 1);
             if (hq < lq)
@@ -201,7 +181,7 @@ static uint64_t count_samples(const cbct_geom_desc &d, const std::vector<double>
             for (int iv = 0; iv < d.nv; ++iv) {
                 double Vz = (d.off_v_mm + (iv - 0.5 * (d.nv - 1)) * d.dv_mm) / d.vz_mm;
                 int64_t lk, hk;
-                open_range(Kb + t0 * Vz, tau * Vz, -1.0, (double)d.nz, &lk, &hk);
+                open_range(Kb + k.t0 * Vz, k.tau * Vz, -1.0, (double)d.nz, &lk, &hk);
                 int64_t lo = std::max(lq, lk), hi = std::min(hq, hk);
                 if (hi >= lo)
                     total += (uint64_t)(hi - lo + 1);
@@ -211,7 +191,9 @@ static uint64_t count_samples(const cbct_geom_desc &d, const std::vector<double>
     return total;
 }
 
-extern "C" cbct_status cbct_geom_create(const cbct_geom_desc *desc, cbct_geom **out)
+// Everything that needs no device: validation, FP64 tables rounded to FP32,
+// launch plans and the sample count.
+static cbct_status host_setup(const cbct_geom_desc *desc, cbct_geom **out)
 {
     if (!desc || !out)
         return CBCT_E_NULL;
@@ -241,38 +223,10 @@ extern "C" cbct_status cbct_geom_create(const cbct_geom_desc *desc, cbct_geom **
             int is_x;
             column_constants(d, g->angles[a], iu, &g->cols[(size_t)a * d.nu + iu], &is_x);
         }
-    std::vector<float2> rows((size_t)d.nv);
+    g->rows.resize((size_t)d.nv);
     for (int iv = 0; iv < d.nv; ++iv) {
         double V = d.off_v_mm + (iv - 0.5 * (d.nv - 1)) * d.dv_mm;
-        rows[iv] = make_float2((float)(V / d.vz_mm), (float)(V * V));
-    }
-
-    size_t ncol = g->cols.size() * sizeof(ColRec);
-    size_t nang = g->angs.size() * sizeof(AngRec);
-    size_t nrow = rows.size() * sizeof(float2);
-    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    size_t total = up(ncol) + up(nang) + up(nrow);
-
-    hipError_t e = hipGetDevice(&g->device);
-    if (e == hipSuccess)
-        e = hipMalloc(&g->dev_block, total);
-    if (e == hipSuccess) {
-        char *base = (char *)g->dev_block;
-        e = hipMemcpy(base, g->cols.data(), ncol, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(base + up(ncol), g->angs.data(), nang, hipMemcpyHostToDevice);
-        if (e == hipSuccess)
-            e = hipMemcpy(base + up(ncol) + up(nang), rows.data(), nrow, hipMemcpyHostToDevice);
-        g->dev.cols = (const ColRec *)base;
-        g->dev.angs = (const AngRec *)(base + up(ncol));
-        g->dev.rows = (const float2 *)(base + up(ncol) + up(nang));
-    }
-    if (e != hipSuccess) {
-        set_hip_error(e);
-        if (g->dev_block)
-            (void)hipFree(g->dev_block);
-        delete g;
-        return e == hipErrorOutOfMemory ? CBCT_E_ALLOC : CBCT_E_HIP;
+        g->rows[iv] = make_float2((float)(V / d.vz_mm), (float)(V * V));
     }
 
     DevGeom &v = g->dev;
@@ -300,8 +254,84 @@ extern "C" cbct_status cbct_geom_create(const cbct_geom_desc *desc, cbct_geom **
     v.rv0 = (float)(d.off_v_mm / d.vz_mm);
     v.rvs = (float)(d.dv_mm / d.vz_mm);
 
+    plan_host(g);
     g->samples = count_samples(g->desc, g->angles);
     *out = g;
+    return CBCT_OK;
+}
+
+// Upload the tables and the tile list to the current device.
+static hipError_t device_upload(cbct_geom *g)
+{
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t ncol = g->cols.size() * sizeof(ColRec);
+    size_t nang = g->angs.size() * sizeof(AngRec);
+    size_t nrow = g->rows.size() * sizeof(float2);
+    size_t ntile = g->tiles.size() * sizeof(TileRec);
+    size_t total = up(ncol) + up(nang) + up(nrow) + up(ntile);
+    hipError_t e = hipGetDevice(&g->device);
+    if (e == hipSuccess)
+        e = hipMalloc(&g->dev_block, total);
+    if (e != hipSuccess)
+        return e;
+    char *base = (char *)g->dev_block;
+    char *pc = base, *pa = pc + up(ncol), *pr = pa + up(nang), *pt = pr + up(nrow);
+    e = hipMemcpy(pc, g->cols.data(), ncol, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(pa, g->angs.data(), nang, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(pr, g->rows.data(), nrow, hipMemcpyHostToDevice);
+    if (e == hipSuccess && ntile)
+        e = hipMemcpy(pt, g->tiles.data(), ntile, hipMemcpyHostToDevice);
+    g->dev.cols = (const ColRec *)pc;
+    g->dev.angs = (const AngRec *)pa;
+    g->dev.rows = (const float2 *)pr;
+    g->fwd.tiles = ntile ? (const TileRec *)pt : nullptr;
+    return e;
+}
+
+extern "C" cbct_status cbct_geom_create(const cbct_geom_desc *desc, cbct_geom **out)
+{
+    cbct_geom *g = nullptr;
+    cbct_status st = host_setup(desc, &g);
+    if (st != CBCT_OK)
+        return st;
+    hipError_t e = device_upload(g);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        cbct_geom_destroy(g);
+        return e == hipErrorOutOfMemory ? CBCT_E_ALLOC : CBCT_E_HIP;
+    }
+    *out = g;
+    return CBCT_OK;
+}
+
+extern "C" cbct_status cbct_geom_create_host(const cbct_geom_desc *desc, cbct_geom **out)
+{
+    return host_setup(desc, out);
+}
+
+extern "C" cbct_status cbct_geom_table(const cbct_geom *g, int which, void *dst, size_t cap,
+                                       size_t *bytes)
+{
+    if (!g || !bytes)
+        return CBCT_E_NULL;
+    const void *src = nullptr;
+    size_t n = 0;
+    switch (which) {
+    case 0: src = g->cols.data(); n = g->cols.size() * sizeof(ColRec); break;
+    case 1: src = g->angs.data(); n = g->angs.size() * sizeof(AngRec); break;
+    case 2: src = g->rows.data(); n = g->rows.size() * sizeof(float2); break;
+    case 3: src = g->tiles.data(); n = g->tiles.size() * sizeof(TileRec); break;
+    case 4: src = &g->dev; n = offsetof(DevGeom, cols); break;
+    default: return CBCT_E_ARG;
+    }
+    *bytes = n;
+    if (dst) {
+        if (cap < n)
+            return CBCT_E_SHAPE;
+        std::memcpy(dst, src, n);
+    }
     return CBCT_OK;
 }
 

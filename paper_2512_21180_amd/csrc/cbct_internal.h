@@ -47,6 +47,34 @@ struct DevGeom {
     const AngRec *angs;  // [n_angles]
 };
 
+// One forward work item: a tile of up to 64 columns x TV rows of one angle,
+// all sampled along the same axis, swept over planes [p_lo, p_hi].
+struct TileRec {
+    int a, cls;        // angle index; 0 = x planes, 1 = y planes
+    int u0, nu_t;      // first column, column count (<= 64)
+    int v0, nv_t;      // first row, row count (<= TV)
+    int p_lo, p_hi;    // planes whose staging box meets the padded volume
+};
+static_assert(sizeof(TileRec) == 32, "TileRec layout");
+
+// Forward plan: LDS box per plane is BQ (in-plane) x BK (z) voxels.
+struct FwdPlan {
+    bool ok = false;   // false: fall back to the one-thread-per-ray kernel
+    int R = 4;         // rays per thread along v (TV = 4 R)
+    int BQ = 0, BK = 0;
+    int n_tiles = 0;   // padded to a multiple of 8 (padding tiles have nu_t = 0)
+    const TileRec *tiles = nullptr;   // device
+};
+
+// Adjoint plan: bricks of 8 x 8 x 16 voxels; per angle the brick's panel
+// footprint (at most W x H pixels, taps included) is staged in LDS.
+struct AdjPlan {
+    bool ok = false;   // false: fall back to the one-thread-per-voxel kernel
+    int W = 0, H = 0;  // footprint bounds (columns, rows)
+    int WS = 0;        // LDS row stride (floats)
+    int NTmax = 0;     // largest row-tap count
+};
+
 }  // namespace cbct
 
 struct cbct_geom {
@@ -59,16 +87,66 @@ struct cbct_geom {
     // Host copies, kept for the batch scheduler and for tests.
     std::vector<cbct::ColRec> cols;
     std::vector<cbct::AngRec> angs;
+    std::vector<float2> rows;
+    std::vector<cbct::TileRec> tiles;
+    cbct::FwdPlan fwd;               // fwd.tiles points into dev_block
+    cbct::AdjPlan adj;
 };
 
 namespace cbct {
 
 void set_hip_error(hipError_t e);
 
-// Kernel launchers (cbct_kernels.hip).  They assume validated arguments.
-hipError_t launch_forward(const DevGeom &g, const void *vol, cbct_dtype vt, void *sino,
+// FP64 constants of the rays of column iu at source angle (c, s): sampling
+// axis and the closed-form lines of the in-plane index q(p) = pb + p ps and
+// ray parameter t(p) = t0 + p tau over plane index p.
+struct Col64 {
+    bool xm;             // sampled on x planes
+    double dx, dy;       // ray direction (xy part)
+    double pb, ps, t0, tau;
+};
+
+inline Col64 col_consts64(const cbct_geom_desc &d, double c, double s, int iu)
+{
+    Col64 r;
+    double U = d.off_u_mm + (iu - 0.5 * (d.nu - 1)) * d.du_mm;
+    r.dx = -d.sdd_mm * c - U * s;
+    r.dy = -d.sdd_mm * s + U * c;
+    r.xm = (r.dx < 0 ? -r.dx : r.dx) >= (r.dy < 0 ? -r.dy : r.dy);
+    double Sx = d.sid_mm * c, Sy = d.sid_mm * s;
+    double dm = r.xm ? r.dx : r.dy, dq = r.xm ? r.dy : r.dx;
+    double Sm = r.xm ? Sx : Sy, Sq = r.xm ? Sy : Sx;
+    double vm = r.xm ? d.vx_mm : d.vy_mm, vq = r.xm ? d.vy_mm : d.vx_mm;
+    double om = r.xm ? d.origin_mm[0] : d.origin_mm[1];
+    double oq = r.xm ? d.origin_mm[1] : d.origin_mm[0];
+    int nm = r.xm ? d.nx : d.ny, nq = r.xm ? d.ny : d.nx;
+    r.t0 = (om - 0.5 * (nm - 1) * vm - Sm) / dm;
+    r.tau = vm / dm;
+    r.pb = (Sq - oq + r.t0 * dq) / vq + 0.5 * (nq - 1);
+    r.ps = r.tau * dq / vq;
+    return r;
+}
+
+// Plans (cbct_plan.cpp): host FP64 analysis of tile boxes and brick
+// footprints; fills g->tiles, g->fwd and g->adj (no device work).
+void plan_host(cbct_geom *g);
+
+// Kernel launchers.  They assume validated arguments.
+hipError_t launch_forward_simple(const DevGeom &g, const void *vol, cbct_dtype vt, void *sino,
+                                 cbct_dtype st, int channels, hipStream_t s);
+hipError_t launch_adjoint_simple(const DevGeom &g, const void *sino, cbct_dtype st, void *vol,
+                                 cbct_dtype vt, int channels, hipStream_t s);
+hipError_t launch_forward_tiled(const DevGeom &g, const FwdPlan &p, const void *vol,
+                                cbct_dtype vt, void *sino, cbct_dtype st, int channels,
+                                hipStream_t s);
+hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *sino,
+                                cbct_dtype st, void *vol, cbct_dtype vt, int channels,
+                                hipStream_t s);
+
+// Dispatch to the tiled kernels when the plan allows, else the simple ones.
+hipError_t launch_forward(const cbct_geom *g, const void *vol, cbct_dtype vt, void *sino,
                           cbct_dtype st, int channels, hipStream_t s);
-hipError_t launch_adjoint(const DevGeom &g, const void *sino, cbct_dtype st, void *vol,
+hipError_t launch_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st, void *vol,
                           cbct_dtype vt, int channels, hipStream_t s);
 
 }  // namespace cbct

@@ -1,0 +1,217 @@
+// Host-side launch plans of libcbct.so, computed once per geometry in FP64.
+//
+// Forward: the panel of every angle is cut into tiles of up to 64 columns x
+// TV rows that share a sampling axis.  A tile sweeps the voxel-centre planes
+// of that axis; on each plane every ray of the tile lands inside a box of
+// BQ x BK voxels, staged in LDS.  BQ and BK are the largest box extents over
+// all tiles and planes (the extent of the box is a convex function of the
+// plane index, so its maximum is reached on the first or the last plane),
+// widened by the rounding margins the kernel relies on.
+//
+// Adjoint: the volume is cut into 8 x 8 x 16 bricks.  For every angle a
+// brick's support (voxel centres +- one pitch) projects onto the panel inside
+// a W x H window that is staged in LDS; W and H are the largest windows over
+// all bricks and angles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "cbct_internal.h"
+
+namespace cbct {
+
+namespace {
+
+constexpr int kTU = 64;           // tile columns (one wavefront)
+constexpr int kMaxBox = 1024;     // staged voxels per plane (4 per thread)
+constexpr int kBI = 8, kBJ = 8, kBK = 16;
+constexpr size_t kAdjLdsBudget = 64 * 1024;
+
+struct TileBuild {
+    std::vector<TileRec> tiles;
+    int BQ = 0, BK = 0;
+};
+
+double row_vz(const cbct_geom_desc &d, int iv)
+{
+    return (d.off_v_mm + (iv - 0.5 * (d.nv - 1)) * d.dv_mm) / d.vz_mm;
+}
+
+TileBuild make_tiles(const cbct_geom *g, int TV)
+{
+    const cbct_geom_desc &d = g->desc;
+    const double Kb = 0.5 * (d.nz - 1) - d.origin_mm[2] / d.vz_mm;
+    TileBuild tb;
+    int maxq = 0, maxk = 0;
+    for (int a = 0; a < d.n_angles; ++a) {
+        const double c = std::cos(g->angles[a]), s = std::sin(g->angles[a]);
+        const AngRec &ar = g->angs[a];
+        // column ranges of one sampling axis: x planes [x_lo, x_hi), y planes elsewhere
+        int ranges[3][3] = {{0, ar.x_lo, 1}, {ar.x_lo, ar.x_hi, 0}, {ar.x_hi, d.nu, 1}};
+        for (auto &rg : ranges) {
+            for (int u0 = rg[0]; u0 < rg[1]; u0 += kTU) {
+                const int nu_t = std::min(kTU, rg[1] - u0);
+                const Col64 cA = col_consts64(d, c, s, u0);
+                const Col64 cB = col_consts64(d, c, s, u0 + nu_t - 1);
+                const int cls = rg[2];
+                const int nm = cls ? d.ny : d.nx, nq = cls ? d.nx : d.ny;
+                for (int v0 = 0; v0 < d.nv; v0 += TV) {
+                    const int nv_t = std::min(TV, d.nv - v0);
+                    const double zA = row_vz(d, v0), zB = row_vz(d, v0 + nv_t - 1);
+                    auto box = [&](double p, double *q0, double *q1, double *k0, double *k1) {
+                        double qa = cA.pb + p * cA.ps, qb = cB.pb + p * cB.ps;
+                        double ta = cA.t0 + p * cA.tau, tb = cB.t0 + p * cB.tau;
+                        double ks[4] = {Kb + ta * zA, Kb + ta * zB, Kb + tb * zA, Kb + tb * zB};
+                        *q0 = std::min(qa, qb);
+                        *q1 = std::max(qa, qb);
+                        *k0 = *std::min_element(ks, ks + 4);
+                        *k1 = *std::max_element(ks, ks + 4);
+                    };
+                    for (double p : {0.0, (double)(nm - 1)}) {
+                        double q0, q1, k0, k1;
+                        box(p, &q0, &q1, &k0, &k1);
+                        maxq = std::max(maxq, (int)(std::floor(q1) - std::floor(q0)));
+                        maxk = std::max(maxk, (int)(std::floor(k1) - std::floor(k0)));
+                    }
+                    auto meets = [&](int p) {
+                        double q0, q1, k0, k1;
+                        box((double)p, &q0, &q1, &k0, &k1);
+                        return q1 > -3.0 && q0 < nq + 2.0 && k1 > -3.0 && k0 < d.nz + 2.0;
+                    };
+                    int lo = 0, hi = nm - 1;
+                    while (lo <= hi && !meets(lo))
+                        ++lo;
+                    while (hi >= lo && !meets(hi))
+                        --hi;
+                    TileRec t;
+                    t.a = a;
+                    t.cls = cls;
+                    t.u0 = u0;
+                    t.nu_t = nu_t;
+                    t.v0 = v0;
+                    t.nv_t = nv_t;
+                    t.p_lo = lo;
+                    t.p_hi = hi;
+                    tb.tiles.push_back(t);
+                }
+            }
+        }
+    }
+    // Kernel box origin is floor(min) - 1 and it reads index floor(q) + 1;
+    // one more voxel on each side covers FP32 rounding of the corner lines.
+    tb.BQ = maxq + 5;
+    tb.BK = maxk + 5;
+    return tb;
+}
+
+// Panel footprint (columns, rows) of the support box of voxel ranges
+// [i0,i1] x [j0,j1] x [k0,k1] at angle th, in FP64, with the kernel's margins.
+void footprint(const cbct_geom_desc &d, double th, int i0, int i1, int j0, int j1, int k0, int k1,
+               int nt, int *W, int *H)
+{
+    const double c = std::cos(th), s = std::sin(th);
+    auto cx = [&](double i) { return d.origin_mm[0] + (i - 0.5 * (d.nx - 1)) * d.vx_mm; };
+    auto cy = [&](double j) { return d.origin_mm[1] + (j - 0.5 * (d.ny - 1)) * d.vy_mm; };
+    auto cz = [&](double k) { return d.origin_mm[2] + (k - 0.5 * (d.nz - 1)) * d.vz_mm; };
+    double xs[2] = {cx(i0) - d.vx_mm, cx(i1) + d.vx_mm};
+    double ys[2] = {cy(j0) - d.vy_mm, cy(j1) + d.vy_mm};
+    double zs[2] = {cz(k0) - d.vz_mm, cz(k1) + d.vz_mm};
+    double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
+    for (double x : xs)
+        for (double y : ys) {
+            double den = c * x + s * y - d.sid_mm;
+            double lam = -d.sdd_mm / den;
+            double u = (lam * (-s * x + c * y) - d.off_u_mm) / d.du_mm + 0.5 * (d.nu - 1);
+            umin = std::min(umin, u);
+            umax = std::max(umax, u);
+            for (double z : zs) {
+                double v = (lam * z - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
+                vmin = std::min(vmin, v);
+                vmax = std::max(vmax, v);
+            }
+        }
+    // kernel: [floor(umin)-1, ceil(umax)+1] x [floor(vmin)-2, ceil(vmax)+2+nt],
+    // plus one for FP32 rounding on each side
+    *W = (int)(std::ceil(umax) - std::floor(umin)) + 3 + 2;
+    *H = (int)(std::ceil(vmax) - std::floor(vmin)) + 5 + nt + 2;
+}
+
+}  // namespace
+
+void plan_host(cbct_geom *g)
+{
+    const cbct_geom_desc &d = g->desc;
+
+    // ---- forward tiles
+    g->fwd = FwdPlan{};
+    g->tiles.clear();
+    TileBuild tb;
+    int R = 0;
+    for (int r : {4, 2, 1}) {
+        tb = make_tiles(g, 4 * r);
+        if (tb.BQ * tb.BK <= kMaxBox) {
+            R = r;
+            break;
+        }
+    }
+    if (R > 0) {
+        while (tb.tiles.size() % 8) {
+            TileRec pad{};
+            pad.nu_t = 0;
+            pad.p_lo = 1;
+            pad.p_hi = 0;
+            tb.tiles.push_back(pad);
+        }
+        g->fwd.ok = true;
+        g->fwd.R = R;
+        g->fwd.BQ = tb.BQ;
+        g->fwd.BK = tb.BK;
+        g->fwd.n_tiles = (int)tb.tiles.size();
+        g->tiles = std::move(tb.tiles);
+    }
+
+    // ---- adjoint bricks
+    g->adj = AdjPlan{};
+    double hx = 0.5 * (d.nx + 1) * d.vx_mm, hy = 0.5 * (d.ny + 1) * d.vy_mm;
+    double R_sup = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        double x = d.origin_mm[0] + ((q & 1) ? hx : -hx);
+        double y = d.origin_mm[1] + ((q & 2) ? hy : -hy);
+        R_sup = std::max(R_sup, std::sqrt(x * x + y * y));
+    }
+    const double t_min = (d.sid_mm - R_sup) / d.sdd_mm;
+    const double rvs = d.dv_mm / d.vz_mm;
+    const int NT = (int)std::floor(2.0 / (t_min * rvs)) + 3;
+    int W = 0, H = 0;
+    const int nbx = (d.nx + kBI - 1) / kBI, nby = (d.ny + kBJ - 1) / kBJ;
+    const int nbz = (d.nz + kBK - 1) / kBK;
+    // the widest window occurs at any height; the tallest in the top or
+    // bottom layer of bricks (perspective grows with |z|)
+    int zl[3] = {0, nbz / 2, nbz - 1};
+    for (int a = 0; a < d.n_angles; ++a)
+        for (int by = 0; by < nby; ++by)
+            for (int bx = 0; bx < nbx; ++bx)
+                for (int bz : zl) {
+                    int w, h;
+                    footprint(d, g->angles[a], bx * kBI, std::min(bx * kBI + kBI, d.nx) - 1,
+                              by * kBJ, std::min(by * kBJ + kBJ, d.ny) - 1, bz * kBK,
+                              std::min(bz * kBK + kBK, d.nz) - 1, NT, &w, &h);
+                    W = std::max(W, w);
+                    H = std::max(H, h);
+                }
+    W = std::min(W, d.nu + 4);
+    H = std::min(H, d.nv + NT + 8);
+    int WS = (W + 3) & ~3;
+    size_t lds = (size_t)H * WS * sizeof(float) + (size_t)W * 4 * sizeof(float);
+    if (lds <= kAdjLdsBudget) {
+        g->adj.ok = true;
+        g->adj.W = W;
+        g->adj.H = H;
+        g->adj.WS = WS;
+        g->adj.NTmax = NT;
+    }
+}
+
+}  // namespace cbct

@@ -1,6 +1,8 @@
-// HIP kernels of libcbct.so for gfx950: the plane-sampled cone-beam forward
-// projector A and its transpose A^T as a gather (arXiv 2512.21180, Sec. 2.2:
-// projection operator P and backprojection P*).
+// Reference-shaped HIP kernels of libcbct.so (gfx950): one thread per ray for
+// the forward projector A and one thread per voxel gathering over every
+// angle for A^T (arXiv 2512.21180, Sec. 2.2: projection operator P and
+// backprojection P*).  They serve geometries whose footprints exceed the
+// LDS limits of the tiled kernels.
 //
 // Both kernels evaluate the same FP32 expressions for every weight:
 //   q  = fma(p, ps, pb)                 in-plane fractional index on plane p
@@ -11,41 +13,10 @@
 #include <hip/hip_runtime.h>
 
 #include "cbct_internal.h"
+#include "cbct_storage.h"
 
 namespace cbct {
 namespace {
-
-// ---- storage conversions ---------------------------------------------------
-
-struct F32 {
-    using T = float;
-    __device__ static float ld(const T *p, size_t i) { return p[i]; }
-    __device__ static void st(T *p, size_t i, float v) { p[i] = v; }
-};
-
-struct BF16 {
-    using T = uint16_t;
-    __device__ static float ld(const T *p, size_t i)
-    {
-        return __uint_as_float(((uint32_t)p[i]) << 16);
-    }
-    __device__ static void st(T *p, size_t i, float v)
-    {
-        uint32_t b = __float_as_uint(v);
-        uint32_t r;
-        if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))
-            r = (b >> 16) | 0x0040u;                       // quiet NaN
-        else
-            r = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;    // round to nearest even
-        p[i] = (uint16_t)r;
-    }
-};
-
-struct F16 {
-    using T = _Float16;
-    __device__ static float ld(const T *p, size_t i) { return (float)p[i]; }
-    __device__ static void st(T *p, size_t i, float v) { p[i] = (_Float16)v; }
-};
 
 // ---- forward: one thread per ray -------------------------------------------
 
@@ -207,7 +178,7 @@ adjoint_simple(DevGeom g, const typename SS::T *__restrict__ sino, typename VS::
 
 }  // namespace
 
-hipError_t launch_forward(const DevGeom &g, const void *vol, cbct_dtype vt, void *sino,
+hipError_t launch_forward_simple(const DevGeom &g, const void *vol, cbct_dtype vt, void *sino,
                           cbct_dtype st, int channels, hipStream_t s)
 {
     dim3 block(256);
@@ -227,7 +198,7 @@ hipError_t launch_forward(const DevGeom &g, const void *vol, cbct_dtype vt, void
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const DevGeom &g, const void *sino, cbct_dtype st, void *vol,
+hipError_t launch_adjoint_simple(const DevGeom &g, const void *sino, cbct_dtype st, void *vol,
                           cbct_dtype vt, int channels, hipStream_t s)
 {
     const size_t nvox = (size_t)g.nx * g.ny * g.nz;

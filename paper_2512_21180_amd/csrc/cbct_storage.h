@@ -1,0 +1,57 @@
+// Storage conversions for the projector kernels: FP32 arithmetic on FP32,
+// BF16 or FP16 buffers (widened on load, rounded to nearest-even on store).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cbct {
+
+struct F32 {
+    using T = float;
+    __device__ static float ld(const T *p, size_t i) { return p[i]; }
+    __device__ static void st(T *p, size_t i, float v) { p[i] = v; }
+};
+
+struct BF16 {
+    using T = uint16_t;
+    __device__ static float ld(const T *p, size_t i)
+    {
+        return __uint_as_float(((uint32_t)p[i]) << 16);
+    }
+    __device__ static void st(T *p, size_t i, float v)
+    {
+        uint32_t b = __float_as_uint(v);
+        uint32_t r;
+        if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))
+            r = (b >> 16) | 0x0040u;                       // quiet NaN
+        else
+            r = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;    // round to nearest even
+        p[i] = (uint16_t)r;
+    }
+};
+
+struct F16 {
+    using T = _Float16;
+    __device__ static float ld(const T *p, size_t i) { return (float)p[i]; }
+    __device__ static void st(T *p, size_t i, float v) { p[i] = (_Float16)v; }
+};
+
+// Dispatch a functor templated on <VolStorage, SinoStorage> by runtime codes.
+template <class F>
+inline hipError_t dispatch_storage(cbct_dtype vt, cbct_dtype st, F &&f)
+{
+    if (vt == CBCT_F32 && st == CBCT_F32) return f(F32{}, F32{});
+    if (vt == CBCT_BF16 && st == CBCT_BF16) return f(BF16{}, BF16{});
+    if (vt == CBCT_F16 && st == CBCT_F16) return f(F16{}, F16{});
+    if (vt == CBCT_BF16 && st == CBCT_F32) return f(BF16{}, F32{});
+    if (vt == CBCT_F16 && st == CBCT_F32) return f(F16{}, F32{});
+    if (vt == CBCT_F32 && st == CBCT_BF16) return f(F32{}, BF16{});
+    if (vt == CBCT_F32 && st == CBCT_F16) return f(F32{}, F16{});
+    if (vt == CBCT_BF16 && st == CBCT_F16) return f(BF16{}, F16{});
+    if (vt == CBCT_F16 && st == CBCT_BF16) return f(F16{}, BF16{});
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cbct

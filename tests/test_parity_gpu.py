@@ -58,7 +58,14 @@ def _close(got, ref, what):
 # odd sizes: ragged launch tails, both sampling axes, offsets on both axes
 RAGGED = W.geometry(20, 37, 29, 3.3, 2.9, 13, 17, 11, 4.0, vy=3.5, vz=4.5, off_u=31.0,
                     off_v=-7.0, origin=(5.0, -3.0, 2.0))
+# plans outside the tiled kernels' LDS limits run the one-thread-per-output kernels:
+# fine voxels under coarse pixels overflow the forward box, coarse voxels under
+# fine pixels overflow the adjoint window
+FINE_VOX = W.geometry(8, 48, 40, 4.0, 4.0, 40, 40, 40, 0.25)
+COARSE_VOX = W.geometry(8, 300, 200, 0.5, 0.5, 16, 16, 16, 16.0)
 CASES = {
+    "fallback_fwd": FINE_VOX,
+    "fallback_adj": COARSE_VOX,
     "ragged": RAGGED,
     "c1": W.C1,
     "c2_crop": W.cropped(W.C2, n_angles=12, nv=64),
@@ -155,3 +162,11 @@ def test_batch_equals_single(dev):
     bs = cbct.batch_adjoint(geos, ys)
     for geo, y, b in zip(geos, ys, bs):
         assert torch.equal(b, cbct.adjoint(geo, y))
+
+
+def test_fallback_cases_take_the_simple_kernels(dev):
+    torch, cbct = dev
+    assert cbct.Geometry(FINE_VOX).plan_info()["fwd_tiled"] == 0
+    assert cbct.Geometry(COARSE_VOX).plan_info()["adj_bricked"] == 0
+    assert cbct.Geometry(W.C2).plan_info()["fwd_tiled"] == 1
+    assert cbct.Geometry(W.C2).plan_info()["adj_bricked"] == 1

@@ -1,0 +1,279 @@
+"""Host logic of libcbct.so, checked on the CPU through host-only handles.
+
+* the FP32 ray tables agree with the oracle's FP64 ray geometry;
+* the library's FP64 sample count equals the oracle's;
+* an FP32 emulation of the forward kernel's LDS box arithmetic shows every
+  bilinear read inside the staged box, for every tile and plane (sampled
+  tiles at clinical size);
+* an FP32 emulation of the adjoint kernel's panel windows shows every
+  non-zero weight (as the forward kernel computes it) inside the window the
+  adjoint scans, and every window inside the staged LDS region.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2512_21180_amd import workloads as W
+
+RAGGED = W.geometry(20, 37, 29, 3.3, 2.9, 13, 17, 11, 4.0, vy=3.5, vz=4.5, off_u=31.0,
+                    off_v=-7.0, origin=(5.0, -3.0, 2.0))
+GEOMS = {
+    "ragged": RAGGED,
+    "c1": W.C1,
+    "c4": W.C4,
+    "c2": W.C2,
+    "c3_8": W.c3_geometries()[8],
+    "steep_angles": W.geometry(7, 90, 70, 2.0, 2.0, 40, 36, 30, 3.0, off_u=60.0,
+                               angles=np.array([0.1, 0.785398, 0.80, 2.3, 3.9, 5.5, 6.0])),
+}
+
+f32 = np.float32
+
+
+def fma32(a, b, c):
+    return (np.asarray(a, np.float64) * np.asarray(b, np.float64) + np.asarray(c, np.float64)
+            ).astype(np.float32)
+
+
+class Host:
+    def __init__(self, g):
+        from paper_2512_21180_amd import cbct
+        self.cb = cbct
+        lib = cbct.lib()
+        lib.cbct_geom_create_host.argtypes = [ctypes.POINTER(cbct.Desc), ctypes.POINTER(ctypes.c_void_p)]
+        lib.cbct_geom_create_host.restype = ctypes.c_int
+        lib.cbct_geom_table.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        lib.cbct_geom_table.restype = ctypes.c_int
+        lib.cbct_geom_plan_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+        lib.cbct_geom_plan_info.restype = ctypes.c_int
+        desc, keep = cbct.make_desc(g)
+        h = ctypes.c_void_p()
+        assert lib.cbct_geom_create_host(ctypes.byref(desc), ctypes.byref(h)) == 0
+        self.h, self.lib, self.g = h, lib, g
+        self.cols = self.table(0, np.float32).reshape(g["n_angles"], g["nu"], 8)
+        angs = self.table(1, np.uint8)
+        self.ang_cs = angs.view(np.float32).reshape(-1, 4)[:, :2]
+        self.ang_x = angs.view(np.int32).reshape(-1, 4)[:, 2:]
+        self.rows = self.table(2, np.float32).reshape(g["nv"], 2)
+        self.tiles = self.table(3, np.int32).reshape(-1, 8)
+        sc = self.table(4, np.uint8)
+        self.ints = sc[:24].view(np.int32)
+        fl = sc[24:].view(np.float32)
+        names = ["Kb", "vx", "vy", "vz", "ox", "oy", "oz", "sid", "sdd", "du", "dv", "off_u",
+                 "off_v", "cu", "cv", "rv0", "rvs"]
+        self.s = dict(zip(names, fl[:len(names)]))
+        info = (ctypes.c_int * 10)()
+        lib.cbct_geom_plan_info(h, info, 10)
+        self.info = list(info)
+
+    def table(self, which, dtype):
+        n = ctypes.c_size_t()
+        assert self.lib.cbct_geom_table(self.h, which, None, 0, ctypes.byref(n)) == 0
+        buf = np.zeros(n.value, dtype=np.uint8)
+        assert self.lib.cbct_geom_table(self.h, which, buf.ctypes.data, n.value, ctypes.byref(n)) == 0
+        return buf.view(dtype)
+
+    def sample_count(self):
+        s = ctypes.c_uint64()
+        assert self.lib.cbct_sample_count(self.h, ctypes.byref(s)) == 0
+        return s.value
+
+    def close(self):
+        self.lib.cbct_geom_destroy(self.h)
+
+
+@pytest.fixture(scope="module")
+def hosts():
+    out = {k: Host(g) for k, g in GEOMS.items()}
+    yield out
+    for h in out.values():
+        h.close()
+
+
+def test_compute_on_host_handle_is_rejected(hosts):
+    h = hosts["ragged"]
+    assert h.lib.cbct_forward(h.h, ctypes.c_void_p(8), 0, ctypes.c_void_p(8), 0, 1, None) == -7
+
+
+@pytest.mark.parametrize("name", ["ragged", "c1", "c4", "steep_angles"])
+def test_ray_tables_match_oracle_geometry(oracle, hosts, name):
+    g, h = GEOMS[name], hosts[name]
+    o = g["origin"]
+    rng = W.rng(3)
+    for _ in range(200):
+        a, u = int(rng.integers(g["n_angles"])), int(rng.integers(g["nu"]))
+        S, d = oracle.ray(g, a, u, 0)
+        xm = abs(d[0]) >= abs(d[1])
+        assert (h.ang_x[a, 0] <= u < h.ang_x[a, 1]) == xm
+        m, q = (0, 1) if xm else (1, 0)
+        nm, nq = (g["nx"], g["ny"]) if xm else (g["ny"], g["nx"])
+        pm, pq = (g["vx"], g["vy"]) if xm else (g["vy"], g["vx"])
+        rec = h.cols[a, u].astype(np.float64)
+        for p in (0, nm - 1):
+            c_m = o[m] + (p - 0.5 * (nm - 1)) * pm
+            t = (c_m - S[m]) / d[m]
+            qf = (S[q] + t * d[q] - o[q]) / pq + 0.5 * (nq - 1)
+            assert abs(rec[0] + p * rec[1] - qf) <= 2e-6 * max(1.0, abs(qf))
+            assert abs(rec[2] + p * rec[3] - t) <= 2e-6 * abs(t)
+        ds_true = pm * np.linalg.norm(d) / abs(d[m])
+        ds = rec[4] * np.sqrt(rec[5] + h.rows[0, 1])
+        assert abs(ds - ds_true) <= 1e-6 * ds_true
+
+
+@pytest.mark.parametrize("name", ["ragged", "c1", "steep_angles", "c3_8"])
+def test_sample_count_matches_oracle(oracle, hosts, name):
+    assert hosts[name].sample_count() == oracle.sample_count(GEOMS[name])
+
+
+def _fwd_tile_check(h, T):
+    a, cls, u0, nu_t, v0, nv_t, p_lo, p_hi = [int(x) for x in T]
+    if nu_t == 0 or p_lo > p_hi:
+        return 0
+    BQ, BK = h.info[2], h.info[3]
+    Kb = h.s["Kb"]
+    C = h.cols[a, u0:u0 + nu_t]
+    Vz = h.rows[v0:v0 + nv_t, 0]
+    p = np.arange(p_lo, p_hi + 1, dtype=np.float32)[:, None, None]
+    cA, cB = C[0], C[-1]
+    qa, qb = fma32(p, cA[1], cA[0]), fma32(p, cB[1], cB[0])
+    ks = [fma32(p, f32(c[3] * z), fma32(c[2], z, Kb)) for c in (cA, cB) for z in (Vz[0], Vz[-1])]
+    qlo = np.floor(np.minimum(qa, qb)) - 1
+    klo = np.floor(np.minimum(np.minimum(ks[0], ks[1]), np.minimum(ks[2], ks[3]))) - 1
+    q = fma32(p, C[None, :, 1, None], C[None, :, 0, None])                 # [P, U, 1]
+    kb = fma32(C[:, 2, None], Vz[None, :], Kb)                              # [U, V]
+    kss = (C[:, 3, None] * Vz[None, :]).astype(np.float32)
+    k = fma32(p, kss[None], kb[None])                                       # [P, U, V]
+    qi = np.floor(q) - qlo
+    ki = np.floor(k) - klo
+    assert qi.min() >= 0 and qi.max() + 1 <= BQ - 1, (T, qi.min(), qi.max(), BQ)
+    assert ki.min() >= 0 and ki.max() + 1 <= BK - 1, (T, ki.min(), ki.max(), BK)
+    return q.size * nv_t
+
+
+@pytest.mark.parametrize("name", sorted(GEOMS))
+def test_forward_box_indices_stay_in_lds(hosts, name):
+    h = hosts[name]
+    assert h.info[0] == 1, "tiled forward expected"
+    assert h.info[2] * h.info[3] <= 1024
+    tiles = h.tiles
+    if len(tiles) > 1500:
+        rng = W.rng(11)
+        pick = rng.choice(len(tiles), 1200, replace=False)
+        # always include every tile of the angles nearest 45 degrees (widest boxes)
+        ang = np.arctan2(h.ang_cs[:, 1], h.ang_cs[:, 0])
+        diag = np.argsort(np.abs(np.abs(np.sin(2 * ang)) - 1))[:2]
+        pick = np.union1d(pick, np.nonzero(np.isin(tiles[:, 0], diag))[0])
+        tiles = tiles[pick]
+    n = sum(_fwd_tile_check(h, T) for T in tiles)
+    assert n > 0
+
+
+def _adj_brick_check(h, bx, by, bz, angles):
+    g = h.g
+    s = h.s
+    nx, ny, nz, nu, nv = g["nx"], g["ny"], g["nz"], g["nu"], g["nv"]
+    W_, H_, WS, NTmax = h.info[6], h.info[7], h.info[8], h.info[9]
+    Kb, rvs, rv0, cv = s["Kb"], s["rvs"], s["rv0"], s["cv"]
+    i0, i1 = bx * 8, min(bx * 8 + 8, nx) - 1
+    j0, j1 = by * 8, min(by * 8 + 8, ny) - 1
+    k0, k1 = bz * 16, min(bz * 16 + 16, nz) - 1
+
+    def cx(i):
+        return f32(s["ox"] + f32(f32(i) - f32(0.5) * f32(nx - 1)) * s["vx"])
+
+    def cy(j):
+        return f32(s["oy"] + f32(f32(j) - f32(0.5) * f32(ny - 1)) * s["vy"])
+
+    def cz(k):
+        return f32(s["oz"] + f32(f32(k) - f32(0.5) * f32(nz - 1)) * s["vz"])
+
+    def proj(c_, s_, x, y):
+        den = fma32(c_, x, fma32(s_, y, -s["sid"]))
+        lam = f32(-s["sdd"] / den)
+        u = f32(f32(f32(lam * fma32(-s_, x, f32(c_ * y))) - s["off_u"]) / s["du"]) + s["cu"]
+        return f32(u), lam
+
+    checked = 0
+    for a in angles:
+        c_, s_ = h.ang_cs[a]
+        x_lo, x_hi = h.ang_x[a]
+        xs = (f32(cx(i0) - s["vx"]), f32(cx(i1) + s["vx"]))
+        ys = (f32(cy(j0) - s["vy"]), f32(cy(j1) + s["vy"]))
+        zs = (f32(cz(k0) - s["vz"]), f32(cz(k1) + s["vz"]))
+        us, vs_, ts = [], [], []
+        for x in xs:
+            for y in ys:
+                u, lam = proj(c_, s_, x, y)
+                us.append(u)
+                for z in zs:
+                    vs_.append(f32(f32(f32(lam * z) - s["off_v"]) / s["dv"]) + s["cv"])
+                ts.append(f32(f32(s["sid"] - fma32(c_, x, f32(s_ * y))) / s["sdd"]))
+        U0 = max(int(np.floor(min(us))) - 1, 0)
+        U1 = min(min(int(np.ceil(max(us))) + 1, nu - 1), U0 + W_ - 1)
+        NT = min(int(np.floor(f32(2.0) / f32(min(ts) * rvs))) + 3, NTmax)
+        V0 = max(int(np.floor(min(vs_))) - 2, 0)
+        V1 = min(min(int(np.ceil(max(vs_))) + 2, nv - 1), V0 + H_ - NT - 1)
+        if U0 > U1 or V0 > V1:
+            # nothing of this brick may be visible at this angle
+            continue
+        assert U1 - U0 + 1 <= W_ and V1 - V0 + 1 + NT <= H_ and W_ <= WS
+        for i in range(i0, i1 + 1):
+            for j in range(j0, j1 + 1):
+                for cls in (0, 1):
+                    if cls == 0:
+                        if x_lo >= x_hi:
+                            continue
+                        lo_c, hi_c, fp, qv = x_lo, x_hi - 1, f32(i), f32(j)
+                        u1, _ = proj(c_, s_, cx(i), f32(cy(j) - s["vy"]))
+                        u2, _ = proj(c_, s_, cx(i), f32(cy(j) + s["vy"]))
+                        cols_ok = np.arange(x_lo, x_hi)
+                    else:
+                        if x_lo == 0 and x_hi == nu:
+                            continue
+                        lo_c, hi_c, fp, qv = 0, nu - 1, f32(j), f32(i)
+                        u1, _ = proj(c_, s_, f32(cx(i) - s["vx"]), cy(j))
+                        u2, _ = proj(c_, s_, f32(cx(i) + s["vx"]), cy(j))
+                        cols_ok = np.setdiff1d(np.arange(nu), np.arange(x_lo, x_hi))
+                    ul = max(max(int(np.floor(min(u1, u2))), lo_c), U0)
+                    uh = min(min(int(np.ceil(max(u1, u2))), hi_c), U1)
+                    # true in-plane support, as the forward kernel weighs it
+                    C = h.cols[a, cols_ok]
+                    q = fma32(fp, C[:, 1], C[:, 0])
+                    sup = cols_ok[np.abs(q.astype(np.float64) - qv) < 1.0]
+                    assert np.all((sup >= ul) & (sup <= uh)), (a, i, j, cls, sup, ul, uh)
+                    for u in sup:
+                        Cu = h.cols[a, u]
+                        t = fma32(fp, Cu[3], Cu[2])
+                        rt = f32(1.0) / t
+                        Vz = h.rows[:, 0]
+                        kf = fma32(fp, (Cu[3] * Vz).astype(np.float32), fma32(Cu[2], Vz, Kb))
+                        for kk in range(k0, k1 + 1):
+                            rows_sup = np.nonzero(np.abs(kf.astype(np.float64) - kk) < 1.0)[0]
+                            vf = fma32(fma32(f32(kk - 1.0) - Kb, rt, -rv0), f32(1.0) / rvs, cv)
+                            vstart = min(max(int(np.floor(vf)) - 1, V0), V1)
+                            assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)), \
+                                (a, i, j, kk, u, rows_sup, vstart, NT)
+                            checked += len(rows_sup)
+    return checked
+
+
+@pytest.mark.parametrize("name", ["ragged", "c1", "c4", "c2", "steep_angles"])
+def test_adjoint_windows_cover_every_weight(hosts, name):
+    h = hosts[name]
+    g = GEOMS[name]
+    assert h.info[5] == 1, "bricked adjoint expected"
+    nbx, nby, nbz = -(-g["nx"] // 8), -(-g["ny"] // 8), -(-g["nz"] // 16)
+    rng = W.rng(5)
+    n_b = 3 if name in ("c2", "c4") else 6
+    na = g["n_angles"]
+    angs = np.unique(np.concatenate([rng.choice(na, min(na, 6), replace=False),
+                                     [0, na // 8, na // 4 + 1]]))
+    total = 0
+    for _ in range(n_b):
+        b = (int(rng.integers(nbx)), int(rng.integers(nby)), int(rng.integers(nbz)))
+        total += _adj_brick_check(h, *b, angles=[int(x) % na for x in angs])
+    # the central brick is always seen
+    total += _adj_brick_check(h, nbx // 2, nby // 2, nbz // 2, angles=[int(x) % na for x in angs])
+    assert total > 0
