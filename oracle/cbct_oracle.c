@@ -523,3 +523,132 @@ double orc_interp_integral(const orc_geom *g, const double *vol, int a, int iu, 
             }
     return total;
 }
+
+/* ---- noise model of the projection simulator ----------------------------
+ *
+ * Poisson counts and the log transform follow the paper's primary model and
+ * normalisation (Sec. 2.2, noisy primary projections; Sec. 2.4, negative
+ * log of counts over the air scan clamped at 1), in its monochromatic form:
+ * counts ~ Poisson(I0 exp(-p)), y = -log(min(max(counts, 1) / I0, 1)).
+ * Random numbers come from the counter-based generator Philox4x32-10
+ * (Salmon, Moraes, Dror, Shaw, SC'11), written here from its published
+ * definition: ten rounds of two 32x32->64-bit multiplications with
+ * multipliers 0xD2511F53 and 0xCD9E8D57, the high halves xored with the other
+ * counter words and the key, and a Weyl key schedule with increments
+ * 0x9E3779B9 and 0xBB67AE85.  Element i, trial j of generator stream s with
+ * 64-bit seed uses counter (i mod 2^32, i div 2^32, j, s) and key
+ * (seed mod 2^32, seed div 2^32).
+ */
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+        uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
+        c0 = h1 ^ c1 ^ k0;
+        c1 = l1;
+        c2 = h0 ^ c3 ^ k1;
+        c3 = l0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+static void draw(uint64_t seed, uint32_t stream, uint64_t i, uint32_t j, uint32_t w[4])
+{
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(i >> 32), j, stream};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, w);
+}
+
+/* 53-bit uniform in [0, 1) from two words. */
+static double u53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+/*
+ * Poisson variate with mean lam >= 0.  Below 10: inversion of the CDF by
+ * sequential search with one uniform.  From 10 up: the transformed rejection
+ * method with squeeze of Hormann (1993, "The transformed rejection method for
+ * generating Poisson random variables", algorithm PTRS), one (U, V) pair per
+ * trial, trials numbered from 0; after 64 rejected trials the rounded mean
+ * is returned (probability far below 1e-30).
+ */
+int64_t orc_poisson(double lam, uint64_t seed, uint32_t stream, uint64_t i)
+{
+    uint32_t w[4];
+    if (!(lam > 0.0))
+        return 0;
+    if (lam < 10.0) {
+        draw(seed, stream, i, 0, w);
+        double u = u53(w[0], w[1]);
+        double p = exp(-lam), F = p;
+        int64_t k = 0;
+        while (u > F && k < 1000) {
+            k += 1;
+            p *= lam / (double)k;
+            F += p;
+        }
+        return k;
+    }
+    double sl = sqrt(lam), ll = log(lam);
+    double b = 0.931 + 2.53 * sl;
+    double a = -0.059 + 0.02483 * b;
+    double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
+    double v_r = 0.9277 - 3.6224 / (b - 2.0);
+    for (uint32_t j = 0; j < 64; ++j) {
+        draw(seed, stream, i, j, w);
+        double U = u53(w[0], w[1]) - 0.5;
+        double V = u53(w[2], w[3]);
+        double us = 0.5 - fabs(U);
+        double kf = floor((2.0 * a / us + b) * U + lam + 0.43);
+        if (us >= 0.07 && V <= v_r)
+            return (int64_t)kf;
+        if (kf < 0.0 || (us < 0.013 && V > us))
+            continue;
+        double lhs = log(V) + log(inv_alpha) - log(a / (us * us) + b);
+        double rhs = -lam + kf * ll - lgamma(kf + 1.0);
+        if (lhs <= rhs)
+            return (int64_t)kf;
+    }
+    return (int64_t)floor(lam + 0.5);
+}
+
+/* y[i] = -log(min(max(n_i, 1) / I0, 1)), n_i ~ Poisson(I0 exp(-p[i])). */
+void orc_sim_poisson_log(int64_t n, const double *p, double I0, uint64_t seed, uint32_t stream,
+                         int64_t *counts, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = orc_poisson(I0 * exp(-p[i]), seed, stream, (uint64_t)i);
+        if (counts)
+            counts[i] = c;
+        double r = (double)(c < 1 ? 1 : c) / I0;
+        y[i] = -log(r < 1.0 ? r : 1.0);
+    }
+}
+
+/* out[i] = clean[i] + sigma z_i, z_i standard normal by the Box-Muller
+ * transform of the first two 53-bit uniforms of element i (trial 0). */
+void orc_sim_gaussian(int64_t n, const double *clean, double sigma, uint64_t seed, uint32_t stream,
+                      double *out)
+{
+    uint32_t w[4];
+    for (int64_t i = 0; i < n; ++i) {
+        draw(seed, stream, (uint64_t)i, 0, w);
+        double u1 = 1.0 - u53(w[0], w[1]);          /* (0, 1] */
+        double u2 = u53(w[2], w[3]);
+        double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
+        out[i] = clean[i] + sigma * z;
+    }
+}

@@ -84,6 +84,12 @@ def _load():
         lib.orc_siddon_dense.argtypes = [G, P(d)]
         lib.orc_interp_integral.argtypes = [G, P(d), ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.orc_interp_integral.restype = d
+        u32 = ctypes.c_uint32
+        lib.orc_philox4x32_10.argtypes = [P(u32), P(u32), P(u32)]
+        lib.orc_poisson.argtypes = [d, ctypes.c_uint64, u32, ctypes.c_uint64]
+        lib.orc_poisson.restype = i64
+        lib.orc_sim_poisson_log.argtypes = [i64, P(d), d, ctypes.c_uint64, u32, P(i64), P(d)]
+        lib.orc_sim_gaussian.argtypes = [i64, P(d), d, ctypes.c_uint64, u32, P(d)]
         _lib = lib
     return _lib
 
@@ -279,10 +285,10 @@ def cgls(g: dict, y: np.ndarray, iters: int, x0=None, callback=None) -> np.ndarr
     return x
 
 
-def opnorm(g: dict, iters: int = 50, seed: int = 0) -> float:
-    """||A||_2 by power iteration on A^T A (FP64)."""
+def opnorm(g: dict, iters: int = 50, seed: int = 0, x0=None) -> float:
+    """||A||_2 by power iteration on A^T A (FP64), from x0 or a seeded start."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    x = rng.standard_normal(vol_shape(g))
+    x = rng.standard_normal(vol_shape(g)) if x0 is None else np.array(x0, dtype=np.float64)
     lam = 0.0
     for _ in range(iters):
         x /= np.linalg.norm(x)
@@ -298,3 +304,39 @@ def landweber(g: dict, y: np.ndarray, iters: int, omega: float, x0=None) -> np.n
     for _ in range(iters):
         x -= omega * adjoint(g, forward(g, x) - y)
     return x
+
+
+# ---- noise model (Sec. 2.2 noisy primary counts, Sec. 2.4 log transform) ----
+
+def philox4x32_10(counter, key):
+    """One Philox4x32-10 block (Salmon et al. 2011) as four Python ints."""
+    lib = _load()
+    U = ctypes.c_uint32 * 4
+    K = ctypes.c_uint32 * 2
+    out = U()
+    lib.orc_philox4x32_10(U(*[int(c) & 0xffffffff for c in counter]),
+                          K(*[int(k) & 0xffffffff for k in key]), out)
+    return [int(v) for v in out]
+
+
+def poisson(lam: float, seed: int, stream: int, i: int) -> int:
+    """Poisson variate of element i (inversion below 10, PTRS from 10)."""
+    return int(_load().orc_poisson(float(lam), seed, stream, i))
+
+
+def sim_poisson_log(p: np.ndarray, I0: float, seed: int, stream: int = 0):
+    """(y, counts): counts ~ Poisson(I0 exp(-p)), y = -log(min(max(counts,1)/I0, 1))."""
+    lib = _load()
+    pp = np.ascontiguousarray(p, dtype=np.float64).ravel()
+    y = np.zeros_like(pp)
+    c = np.zeros(pp.shape, dtype=np.int64)
+    lib.orc_sim_poisson_log(pp.size, _dp(pp), float(I0), seed, stream, _ip(c), _dp(y))
+    return y.reshape(np.shape(p)), c.reshape(np.shape(p))
+
+
+def sim_gaussian(clean: np.ndarray, sigma: float, seed: int, stream: int = 0) -> np.ndarray:
+    lib = _load()
+    cc = np.ascontiguousarray(clean, dtype=np.float64).ravel()
+    out = np.zeros_like(cc)
+    lib.orc_sim_gaussian(cc.size, _dp(cc), float(sigma), seed, stream, _dp(out))
+    return out.reshape(np.shape(clean))

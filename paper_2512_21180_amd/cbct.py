@@ -65,6 +65,10 @@ def _load():
     lib.cbct_axpy_ratio.argtypes = [sz, vp, vp, vp, vp, dp, vp]
     lib.cbct_xpay_ratio.argtypes = [sz, vp, vp, vp, vp, vp]
     lib.cbct_axpby.argtypes = [sz, vp, ctypes.c_float, vp, ctypes.c_float, vp, vp]
+    u32, u64 = ctypes.c_uint32, ctypes.c_uint64
+    lib.cbct_philox_blocks.argtypes = [sz, u64, u32, vp, vp]
+    lib.cbct_sim_poisson_log.argtypes = [sz, vp, vp, vp, dp, u64, u32, vp]
+    lib.cbct_sim_gaussian.argtypes = [sz, vp, vp, dp, u64, u32, vp]
     lib.cbct_error_string.argtypes = [i32]
     lib.cbct_error_string.restype = ctypes.c_char_p
     lib.cbct_last_hip_error.argtypes = []
@@ -72,7 +76,8 @@ def _load():
     for name in ("cbct_geom_create", "cbct_geom_destroy", "cbct_sample_count", "cbct_geom_sizes",
                  "cbct_forward", "cbct_adjoint", "cbct_batch_forward", "cbct_batch_adjoint",
                  "cbct_geom_plan_info", "cbct_geom_create_host", "cbct_geom_table",
-                 "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby"):
+                 "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby",
+                 "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -310,3 +315,36 @@ def axpby(z, alpha, x, beta, y):
     _check(_lib.cbct_axpby(z.numel(), _f32(z, "z"), float(alpha), _f32(x, "x"), float(beta),
                            _f32(y, "y"), _stream(z.device)), "cbct_axpby")
     return z
+
+
+# ---- simulator (cbct_sim.h) ------------------------------------------------
+
+def philox_blocks(n_blocks: int, seed: int, stream_id: int, device="cuda") -> torch.Tensor:
+    """[n_blocks, 4] raw Philox4x32-10 words (as int32 bit patterns)."""
+    out = torch.empty((n_blocks, 4), dtype=torch.int32, device=device)
+    _check(_lib.cbct_philox_blocks(n_blocks, seed, stream_id, ctypes.c_void_p(out.data_ptr()),
+                                   _stream(out.device)), "cbct_philox_blocks")
+    return out
+
+
+def sim_poisson_log(p: torch.Tensor, I0: float, seed: int, stream_id: int = 0,
+                    out: torch.Tensor | None = None, counts: bool = False):
+    """y = -log(min(max(Poisson(I0 exp(-p)), 1) / I0, 1)); returns y (and counts)."""
+    if out is None:
+        out = torch.empty_like(p)
+    c = torch.empty(p.shape, dtype=torch.int64, device=p.device) if counts else None
+    _check(_lib.cbct_sim_poisson_log(p.numel(), _f32(p, "p"), _f32(out, "out"),
+                                     ctypes.c_void_p(c.data_ptr()) if c is not None else None,
+                                     float(I0), seed, stream_id, _stream(p.device)),
+           "cbct_sim_poisson_log")
+    return (out, c) if counts else out
+
+
+def sim_gaussian(clean: torch.Tensor, sigma: float, seed: int, stream_id: int = 0,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty_like(clean)
+    _check(_lib.cbct_sim_gaussian(clean.numel(), _f32(clean, "clean"), _f32(out, "out"),
+                                  float(sigma), seed, stream_id, _stream(clean.device)),
+           "cbct_sim_gaussian")
+    return out

@@ -18,6 +18,8 @@
 // most NT rows; the taps use the clamped hat, so rows past the run add zero.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "cbct_internal.h"
 #include "cbct_storage.h"
 
@@ -45,22 +47,17 @@ __device__ inline void project_xy(const DevGeom &g, float c, float s, float x, f
     u = (lam * fmaf(-s, x, c * y) - g.off_u) / g.du + g.cu;
 }
 
+// Gather one brick (index b) of one channel: y is that channel's sinogram,
+// vol that channel's volume.  `lds` holds the panel window and column table.
 template <class SS, class VS>
-__global__ void __launch_bounds__(kThreads)
-adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
-              typename VS::T *__restrict__ vol)
+__device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__restrict__ y,
+                             typename VS::T *__restrict__ vol, float *lds)
 {
-    extern __shared__ float lds[];
     const DevGeom &g = A.g;
     float *yt = lds;                                    // [H][WS] ds-weighted panel window
     float4 *cr = (float4 *)(lds + (size_t)A.H * A.WS);  // [W] (pb, ps, t0, tau)
 
-    const int b = blockIdx.x;
     const int bx = b % A.nbx, by = (b / A.nbx) % A.nby, bz = b / (A.nbx * A.nby);
-    const int ch = blockIdx.y;
-    const size_t nvox = (size_t)g.nx * g.ny * g.nz;
-    const size_t nsino = (size_t)g.n_angles * g.nv * g.nu;
-    const typename SS::T *y = sino + ch * nsino;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int i = bx * kBI + (lane & 7), j = by * kBJ + (lane >> 3);
@@ -83,6 +80,7 @@ adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
     const float inv_rvs = 1.0f / g.rvs;
     float acc[kV] = {0.0f, 0.0f, 0.0f, 0.0f};
 
+    __syncthreads();   // the previous work item's readers of lds are done
     for (int a = 0; a < g.n_angles; ++a) {
         const AngRec ar = g.angs[a];
         // ---- panel window of the brick (uniform)
@@ -190,26 +188,101 @@ adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
         for (int n = 0; n < kV; ++n) {
             const int k = k0 + n;
             if (k < g.nz)
-                VS::st(vol, ch * nvox + ((size_t)k * g.ny + j) * g.nx + i, acc[n]);
+                VS::st(vol, ((size_t)k * g.ny + j) * g.nx + i, acc[n]);
         }
+    }
+}
+
+template <class SS, class VS>
+__global__ void __launch_bounds__(kThreads)
+adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
+              typename VS::T *__restrict__ vol)
+{
+    extern __shared__ float lds[];
+    const int ch = blockIdx.y;
+    const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
+    const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
+    gather_brick<SS, VS>(A, blockIdx.x, sino + ch * nsino, vol + ch * nvox, lds);
+}
+
+// ---- batched adjoint: one persistent launch over (case, brick) items -------
+
+struct AdjCase {
+    BrickArgs A;
+    const void *sino;
+    void *vol;
+};
+
+struct BatchAdjArgs {
+    int n_cases, n_items;
+    int first[kMaxBatch + 1];
+    AdjCase c[kMaxBatch];
+};
+
+template <class SS, class VS>
+__global__ void __launch_bounds__(kThreads)
+adjoint_batch(BatchAdjArgs B)
+{
+    extern __shared__ float lds[];
+    for (int item = blockIdx.x; item < B.n_items; item += gridDim.x) {
+        int cs = 0;
+        while (cs + 1 < B.n_cases && item >= B.first[cs + 1])
+            ++cs;
+        const AdjCase &C = B.c[cs];
+        gather_brick<SS, VS>(C.A, item - B.first[cs], (const typename SS::T *)C.sino,
+                             (typename VS::T *)C.vol, lds);
     }
 }
 
 }  // namespace
 
+static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
+{
+    return BrickArgs{g, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI, (g.ny + kBJ - 1) / kBJ,
+                     (g.nz + kBK - 1) / kBK};
+}
+
+static size_t brick_lds(const AdjPlan &p)
+{
+    return ((size_t)p.H * p.WS + (size_t)p.W * 4) * sizeof(float);
+}
+
 hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *sino,
                                 cbct_dtype st, void *vol, cbct_dtype vt, int channels,
                                 hipStream_t s)
 {
-    BrickArgs A{g, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI, (g.ny + kBJ - 1) / kBJ,
-                (g.nz + kBK - 1) / kBK};
-    const size_t lds = ((size_t)p.H * p.WS + (size_t)p.W * 4) * sizeof(float);
+    BrickArgs A = brick_args(g, p);
     dim3 grid(A.nbx * A.nby * A.nbz, channels), block(kThreads);
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
-        hipLaunchKernelGGL((adjoint_brick<SS, VS>), grid, block, lds, s, A,
+        hipLaunchKernelGGL((adjoint_brick<SS, VS>), grid, block, brick_lds(p), s, A,
                            (const typename SS::T *)sino, (typename VS::T *)vol);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adjoint_batch(int n, const cbct_geom *const *gs, const void *const *sinos,
+                                void *const *vols, cbct_dtype st, cbct_dtype vt, hipStream_t s)
+{
+    BatchAdjArgs B{};
+    B.n_cases = n;
+    size_t lds = 0;
+    int items = 0;
+    for (int i = 0; i < n; ++i) {
+        const cbct_geom *g = gs[i];
+        B.first[i] = items;
+        B.c[i] = AdjCase{brick_args(g->dev, g->adj), sinos[i], vols[i]};
+        items += B.c[i].A.nbx * B.c[i].A.nby * B.c[i].A.nbz;
+        lds = std::max(lds, brick_lds(g->adj));
+    }
+    B.first[n] = items;
+    B.n_items = items;
+    const int grid = std::min(items, 256 * 4);
+    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
+        using VS = decltype(vs);
+        using SS = decltype(ss);
+        hipLaunchKernelGGL((adjoint_batch<SS, VS>), dim3(grid), dim3(kThreads), lds, s, B);
         return hipGetLastError();
     });
 }

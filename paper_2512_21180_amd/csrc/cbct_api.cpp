@@ -104,6 +104,9 @@ static cbct_status check_batch(int n, const cbct_geom *const *g, const void *con
     return CBCT_OK;
 }
 
+// Batches run as persistent launches of up to kMaxBatch cases each; a case
+// whose plan fell back to the one-thread-per-output kernels is launched on
+// its own (same arithmetic, so the results are the same bits either way).
 extern "C" cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,
                                           void *const *sinos, cbct_dtype vt, cbct_dtype st,
                                           void *stream)
@@ -111,12 +114,31 @@ extern "C" cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, cons
     cbct_status s = check_batch(n, g, vols, (const void *const *)sinos, vt, st);
     if (s != CBCT_OK)
         return s;
+    hipStream_t hs = (hipStream_t)stream;
+    const cbct_geom *gg[kMaxBatch];
+    const void *xx[kMaxBatch];
+    void *yy[kMaxBatch];
+    int m = 0;
+    auto flush = [&]() -> hipError_t {
+        hipError_t e = m ? launch_forward_batch(m, gg, xx, yy, vt, st, hs) : hipSuccess;
+        m = 0;
+        return e;
+    };
     for (int i = 0; i < n; ++i) {
-        hipError_t e = launch_forward(g[i], vols[i], vt, sinos[i], st, 1, (hipStream_t)stream);
+        hipError_t e = hipSuccess;
+        if (!g[i]->fwd.ok) {
+            e = launch_forward(g[i], vols[i], vt, sinos[i], st, 1, hs);
+        } else {
+            gg[m] = g[i];
+            xx[m] = vols[i];
+            yy[m] = sinos[i];
+            if (++m == kMaxBatch)
+                e = flush();
+        }
         if (e != hipSuccess)
             return finish(e);
     }
-    return CBCT_OK;
+    return finish(flush());
 }
 
 extern "C" cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, const void *const *sinos,
@@ -126,12 +148,31 @@ extern "C" cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, cons
     cbct_status s = check_batch(n, g, sinos, (const void *const *)vols, st, vt);
     if (s != CBCT_OK)
         return s;
+    hipStream_t hs = (hipStream_t)stream;
+    const cbct_geom *gg[kMaxBatch];
+    const void *yy[kMaxBatch];
+    void *xx[kMaxBatch];
+    int m = 0;
+    auto flush = [&]() -> hipError_t {
+        hipError_t e = m ? launch_adjoint_batch(m, gg, yy, xx, st, vt, hs) : hipSuccess;
+        m = 0;
+        return e;
+    };
     for (int i = 0; i < n; ++i) {
-        hipError_t e = launch_adjoint(g[i], sinos[i], st, vols[i], vt, 1, (hipStream_t)stream);
+        hipError_t e = hipSuccess;
+        if (!g[i]->adj.ok) {
+            e = launch_adjoint(g[i], sinos[i], st, vols[i], vt, 1, hs);
+        } else {
+            gg[m] = g[i];
+            yy[m] = sinos[i];
+            xx[m] = vols[i];
+            if (++m == kMaxBatch)
+                e = flush();
+        }
         if (e != hipSuccess)
             return finish(e);
     }
-    return CBCT_OK;
+    return finish(flush());
 }
 
 extern "C" cbct_status cbct_geom_plan_info(const cbct_geom *g, int *info, int n)

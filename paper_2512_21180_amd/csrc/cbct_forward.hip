@@ -7,8 +7,8 @@
 // R rays of one column and shares their in-plane interpolation index.
 //
 // The tile sweeps the voxel-centre planes of its axis.  On plane p every ray
-// of the tile lands inside a BQ x BK box of (in-plane, z) voxels whose origin
-// follows the corner rays; the box is staged in LDS (zero outside the
+// of the tile lands inside a box of at most 64 (in-plane) x 32 (z) voxels
+// spanned by the corner rays; the box is staged in LDS (zero outside the
 // volume) one plane ahead of its use, double-buffered, one barrier per plane.
 // Each sample is the bilinear interpolant read from LDS; each ray keeps its
 // own running sum in a register, so the summation order is the plane order
@@ -17,6 +17,8 @@
 // workgroups sharing an L2 work on neighbouring tiles of the same angle.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "cbct_internal.h"
 #include "cbct_storage.h"
 
@@ -24,44 +26,33 @@ namespace cbct {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxStage = 4;   // staged voxels per thread per plane (BQ*BK <= 1024)
+constexpr int kMaxR = 8;       // rays per thread
+constexpr int kQS = 65;        // LDS row stride (floats): box rows are <= 64 wide
+constexpr int kMaxRows = 32;   // box rows (z) per plane
+constexpr int kSlots = kMaxRows / 4;
 
-struct SweepArgs {
-    DevGeom g;
-    const TileRec *tiles;
-    int n_tiles;
-    int BQ, BK;
-};
-
-template <int R, class VS, class SS>
-__global__ void __launch_bounds__(kThreads)
-forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
-              typename SS::T *__restrict__ sino)
+// Sweep one tile.  R (rays per thread, 1..8) is uniform per tile; the per
+// ray arithmetic does not depend on it, so any launch shape gives the same
+// bits.  `lds` holds two boxes of kMaxRows x kQS floats.
+//
+// On plane p the box spans in-plane indices [qlo, qlo + qw) and z indices
+// [klo, klo + kw), from the corner rays' crossings widened by one voxel for
+// rounding; wave w stages rows w, w + 4, ... with lane l holding column l,
+// so each row is one load per lane.
+template <class VS, class SS>
+__device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R,
+                           const typename VS::T *__restrict__ v,
+                           typename SS::T *__restrict__ sino, float *lds)
 {
-    extern __shared__ float lds[];
-    const DevGeom &g = A.g;
-    // XCD-contiguous tile order: workgroups are dealt to the 8 XCDs round
-    // robin, so XCD x receives ids x, x+8, ...; give it tiles
-    // [x * n/8, (x+1) * n/8).
-    const int nb = gridDim.x;
-    const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    const TileRec T = A.tiles[t];
-    if (T.nu_t == 0)
-        return;
-    const int ch = blockIdx.y;
-    const size_t nvox = (size_t)g.nx * g.ny * g.nz;
-    const size_t nsino = (size_t)g.n_angles * g.nv * g.nu;
-    const typename VS::T *v = vol + ch * nvox;
-
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int ul = min(lane, T.nu_t - 1);
     const ColRec c = g.cols[(size_t)T.a * g.nu + T.u0 + ul];
 
-    float kb[R], ks[R], acc[R];
+    float kb[kMaxR], ks[kMaxR], acc[kMaxR];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int vr = T.v0 + min(w * R + r, T.nv_t - 1);
+    for (int r = 0; r < kMaxR; ++r) {
+        const int vr = T.v0 + min(w * R + min(r, R - 1), T.nv_t - 1);
         const float vz = g.rows[vr].x;
         kb[r] = fmaf(c.t0, vz, g.Kb);
         ks[r] = c.tau * vz;
@@ -77,90 +68,158 @@ forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
     const float kbB0 = fmaf(cB.t0, zA, g.Kb), ksB0 = cB.tau * zA;
     const float kbB1 = fmaf(cB.t0, zB, g.Kb), ksB1 = cB.tau * zB;
 
-    const int BQ = A.BQ, BK = A.BK, box = BQ * BK;
     const bool xp = T.cls == 0;
     const int nq = xp ? g.ny : g.nx;
-    const size_t sp = xp ? 1 : (size_t)g.nx;     // plane stride
-    const size_t sq = xp ? (size_t)g.nx : 1;     // in-plane stride
-    const size_t sk = (size_t)g.nx * g.ny;       // z stride
+    const int sp = xp ? 1 : g.nx;      // plane stride
+    const int sq = xp ? g.nx : 1;      // in-plane stride
+    const int sk = g.nx * g.ny;        // z stride (volumes have < 2^31 voxels)
 
-    // this thread's staged voxels: box cells e = tid + 256 s
-    int eq[kMaxStage], ek[kMaxStage];
-#pragma unroll
-    for (int s = 0; s < kMaxStage; ++s) {
-        const int e = tid + kThreads * s;
-        ek[s] = e / BQ;
-        eq[s] = e - ek[s] * BQ;
-    }
-
-    auto origin = [&](int p, int &qlo, int &klo) {
+    struct Box {
+        int qlo, klo, qw, kw;
+    };
+    auto box_of = [&](int p) {
         const float fp = (float)p;
         const float qa = fmaf(fp, cA.ps, cA.pb), qb = fmaf(fp, cB.ps, cB.pb);
         const float k0 = fmaf(fp, ksA0, kbA0), k1 = fmaf(fp, ksA1, kbA1);
         const float k2 = fmaf(fp, ksB0, kbB0), k3 = fmaf(fp, ksB1, kbB1);
-        qlo = (int)floorf(fminf(qa, qb)) - 1;
-        klo = (int)floorf(fminf(fminf(k0, k1), fminf(k2, k3))) - 1;
+        Box b;
+        b.qlo = (int)floorf(fminf(qa, qb)) - 1;
+        b.klo = (int)floorf(fminf(fminf(k0, k1), fminf(k2, k3))) - 1;
+        b.qw = min((int)floorf(fmaxf(qa, qb)) + 3 - b.qlo, 64);
+        b.kw = min((int)floorf(fmaxf(fmaxf(k0, k1), fmaxf(k2, k3))) + 3 - b.klo, kMaxRows);
+        b.qlo = __builtin_amdgcn_readfirstlane(b.qlo);
+        b.klo = __builtin_amdgcn_readfirstlane(b.klo);
+        b.qw = __builtin_amdgcn_readfirstlane(b.qw);
+        b.kw = __builtin_amdgcn_readfirstlane(b.kw);
+        return b;
     };
-    auto fetch = [&](int p, int qlo, int klo, float (&st)[kMaxStage]) {
+    auto fetch = [&](int p, const Box &b, float (&st)[kSlots]) {
+        const int q = b.qlo + lane;
+        const bool qin = lane < b.qw && (unsigned)q < (unsigned)nq;
+        const int base = q * sq + p * sp;
 #pragma unroll
-        for (int s = 0; s < kMaxStage; ++s) {
+        for (int s = 0; s < kSlots; ++s) {
             st[s] = 0.0f;
-            const int q = qlo + eq[s], k = klo + ek[s];
-            if (tid + kThreads * s < box && q >= 0 && q < nq && k >= 0 && k < g.nz)
-                st[s] = VS::ld(v, (size_t)k * sk + (size_t)q * sq + (size_t)p * sp);
+            const int kk = w + 4 * s;
+            const int k = b.klo + kk;
+            if (kk < b.kw && qin && (unsigned)k < (unsigned)g.nz)
+                st[s] = VS::ld(v, (size_t)(base + k * sk));
         }
     };
 
+    __syncthreads();   // the previous work item's readers of lds are done
     int p = T.p_lo;
-    int qlo = 0, klo = 0;
-    float stage[kMaxStage];
+    Box nb{0, 0, 0, 0};
+    float stage[kSlots];
     if (p <= T.p_hi) {
-        origin(p, qlo, klo);
-        fetch(p, qlo, klo, stage);
+        nb = box_of(p);
+        fetch(p, nb, stage);
     }
     for (; p <= T.p_hi; ++p) {
-        float *buf = lds + (p & 1) * box;
+        float *buf = lds + (p & 1) * (kMaxRows * kQS);
+        const Box cb = nb;
 #pragma unroll
-        for (int s = 0; s < kMaxStage; ++s)
-            if (tid + kThreads * s < box)
-                buf[tid + kThreads * s] = stage[s];
-        const int qc = qlo, kc = klo;
+        for (int s = 0; s < kSlots; ++s)
+            if (w + 4 * s < cb.kw)
+                buf[(w + 4 * s) * kQS + lane] = stage[s];
         __syncthreads();
         if (p < T.p_hi) {
-            origin(p + 1, qlo, klo);
-            fetch(p + 1, qlo, klo, stage);
+            nb = box_of(p + 1);
+            fetch(p + 1, nb, stage);
         }
         const float fp = (float)p;
         const float q = fmaf(fp, c.ps, c.pb);
         const float qf = floorf(q);
         const float wq = q - qf;
-        const int qi = (int)qf - qc;
+        const int qi = (int)qf - cb.qlo;
+        const float kc = (float)cb.klo;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float k = fmaf(fp, ks[r], kb[r]);
-            const float kf = floorf(k);
-            const float wk = k - kf;
-            const int idx = ((int)kf - kc) * BQ + qi;
-            const float v00 = buf[idx], v10 = buf[idx + 1];
-            const float v01 = buf[idx + BQ], v11 = buf[idx + BQ + 1];
-            const float lo = fmaf(wq, v10 - v00, v00);
-            const float hi = fmaf(wq, v11 - v01, v01);
-            acc[r] += fmaf(wk, hi - lo, lo);
+        for (int r = 0; r < kMaxR; ++r) {
+            if (r < R) {
+                const float k = fmaf(fp, ks[r], kb[r]) - kc;
+                const float kf = floorf(k);
+                const float wk = k - kf;
+                const float *row = buf + __mul24((int)kf, kQS) + qi;
+                const float v00 = row[0], v10 = row[1];
+                const float v01 = row[kQS], v11 = row[kQS + 1];
+                const float lo = fmaf(wq, v10 - v00, v00);
+                const float hi = fmaf(wq, v11 - v01, v01);
+                acc[r] += fmaf(wk, hi - lo, lo);
+            }
         }
     }
 
     if (lane < T.nu_t) {
         const float ds0 = c.dsf;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < kMaxR; ++r) {
             const int vr = w * R + r;
-            if (vr < T.nv_t) {
+            if (r < R && vr < T.nv_t) {
                 const int iv = T.v0 + vr;
                 const float ds = ds0 * sqrtf(c.n2 + g.rows[iv].y);
-                SS::st(sino, ch * nsino + ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + lane,
-                       acc[r] * ds);
+                SS::st(sino, ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + lane, acc[r] * ds);
             }
         }
+    }
+}
+
+struct SweepArgs {
+    DevGeom g;
+    const TileRec *tiles;
+    int R;
+};
+
+template <class VS, class SS>
+__global__ void __launch_bounds__(kThreads)
+forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
+              typename SS::T *__restrict__ sino)
+{
+    extern __shared__ float lds[];
+    // XCD-contiguous tile order: workgroups are dealt to the 8 XCDs round
+    // robin, so XCD x receives ids x, x+8, ...; give it tiles
+    // [x * n/8, (x+1) * n/8).
+    const int nb = gridDim.x;
+    const int t = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+    const TileRec T = A.tiles[t];
+    if (T.nu_t == 0)
+        return;
+    const int ch = blockIdx.y;
+    const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
+    const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
+    sweep_tile<VS, SS>(A.g, T, A.R, vol + ch * nvox, sino + ch * nsino, lds);
+}
+
+// ---- batched forward: one persistent launch over (case, tile) items --------
+
+struct FwdCase {
+    DevGeom g;
+    const TileRec *tiles;
+    int R, BQ, BK, n_tiles;
+    const void *vol;
+    void *sino;
+};
+
+struct BatchFwdArgs {
+    int n_cases, n_items;
+    int first[kMaxBatch + 1];   // first item of each case
+    FwdCase c[kMaxBatch];
+};
+
+template <class VS, class SS>
+__global__ void __launch_bounds__(kThreads)
+forward_batch(BatchFwdArgs B)
+{
+    extern __shared__ float lds[];
+    for (int item = blockIdx.x; item < B.n_items; item += gridDim.x) {
+        int cs = 0;
+        while (cs + 1 < B.n_cases && item >= B.first[cs + 1])
+            ++cs;
+        const FwdCase &C = B.c[cs];
+        const TileRec T = C.tiles[item - B.first[cs]];
+        if (T.nu_t == 0)
+            continue;
+        sweep_tile<VS, SS>(C.g, T, C.R, (const typename VS::T *)C.vol, (typename SS::T *)C.sino,
+                           lds);
     }
 }
 
@@ -170,19 +229,41 @@ hipError_t launch_forward_tiled(const DevGeom &g, const FwdPlan &p, const void *
                                 cbct_dtype vt, void *sino, cbct_dtype st, int channels,
                                 hipStream_t s)
 {
-    SweepArgs A{g, p.tiles, p.n_tiles, p.BQ, p.BK};
-    const size_t lds = 2 * (size_t)p.BQ * p.BK * sizeof(float);
+    SweepArgs A{g, p.tiles, p.R};
+    const size_t lds = 2 * (size_t)kMaxRows * kQS * sizeof(float);
     dim3 grid(p.n_tiles, channels), block(kThreads);
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
-        const auto *x = (const typename VS::T *)vol;
-        auto *y = (typename SS::T *)sino;
-        switch (p.R) {
-        case 4: hipLaunchKernelGGL((forward_sweep<4, VS, SS>), grid, block, lds, s, A, x, y); break;
-        case 2: hipLaunchKernelGGL((forward_sweep<2, VS, SS>), grid, block, lds, s, A, x, y); break;
-        default: hipLaunchKernelGGL((forward_sweep<1, VS, SS>), grid, block, lds, s, A, x, y); break;
-        }
+        hipLaunchKernelGGL((forward_sweep<VS, SS>), grid, block, lds, s, A,
+                           (const typename VS::T *)vol, (typename SS::T *)sino);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_forward_batch(int n, const cbct_geom *const *gs, const void *const *vols,
+                                void *const *sinos, cbct_dtype vt, cbct_dtype st, hipStream_t s)
+{
+    BatchFwdArgs B{};
+    B.n_cases = n;
+    size_t lds = 0;
+    int items = 0;
+    for (int i = 0; i < n; ++i) {
+        const cbct_geom *g = gs[i];
+        B.first[i] = items;
+        B.c[i] = FwdCase{g->dev, g->fwd.tiles, g->fwd.R, g->fwd.BQ, g->fwd.BK, g->fwd.n_tiles,
+                         vols[i], sinos[i]};
+        items += g->fwd.n_tiles;
+        lds = 2 * (size_t)kMaxRows * kQS * sizeof(float);
+    }
+    B.first[n] = items;
+    B.n_items = items;
+    // persistent: enough workgroups to fill 256 CUs several times over
+    const int grid = std::min(items, 256 * 8);
+    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
+        using VS = decltype(vs);
+        using SS = decltype(ss);
+        hipLaunchKernelGGL((forward_batch<VS, SS>), dim3(grid), dim3(kThreads), lds, s, B);
         return hipGetLastError();
     });
 }

@@ -143,6 +143,14 @@ hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *
                                 cbct_dtype st, void *vol, cbct_dtype vt, int channels,
                                 hipStream_t s);
 
+// Batched launches: one persistent kernel over all cases' work items.  All
+// cases must have tiled (forward) or bricked (adjoint) plans.
+constexpr int kMaxBatch = 16;
+hipError_t launch_forward_batch(int n, const cbct_geom *const *g, const void *const *vols,
+                                void *const *sinos, cbct_dtype vt, cbct_dtype st, hipStream_t s);
+hipError_t launch_adjoint_batch(int n, const cbct_geom *const *g, const void *const *sinos,
+                                void *const *vols, cbct_dtype st, cbct_dtype vt, hipStream_t s);
+
 // Dispatch to the tiled kernels when the plan allows, else the simple ones.
 hipError_t launch_forward(const cbct_geom *g, const void *vol, cbct_dtype vt, void *sino,
                           cbct_dtype st, int channels, hipStream_t s);

@@ -2,11 +2,12 @@
 //
 // Forward: the panel of every angle is cut into tiles of up to 64 columns x
 // TV rows that share a sampling axis.  A tile sweeps the voxel-centre planes
-// of that axis; on each plane every ray of the tile lands inside a box of
-// BQ x BK voxels, staged in LDS.  BQ and BK are the largest box extents over
-// all tiles and planes (the extent of the box is a convex function of the
-// plane index, so its maximum is reached on the first or the last plane),
-// widened by the rounding margins the kernel relies on.
+// of that axis; on each plane every ray of the tile lands inside a box that
+// the kernel stages in LDS, at most 64 x 32 voxels.  BQ and BK are the
+// largest box extents over all tiles and planes (the extent of the box is a
+// convex function of the plane index, so its maximum is reached on the first
+// or the last plane), widened by the rounding margins the kernel relies on;
+// TV is the largest of 32, 16, 8, 4 rows whose boxes fit.
 //
 // Adjoint: the volume is cut into 8 x 8 x 16 bricks.  For every angle a
 // brick's support (voxel centres +- one pitch) projects onto the panel inside
@@ -25,7 +26,8 @@ namespace cbct {
 namespace {
 
 constexpr int kTU = 64;           // tile columns (one wavefront)
-constexpr int kMaxBox = 1024;     // staged voxels per plane (4 per thread)
+constexpr int kMaxBoxQ = 64;      // staged box: one 64-lane row per z index
+constexpr int kMaxBoxK = 32;      // and at most 32 rows
 constexpr int kBI = 8, kBJ = 8, kBK = 16;
 constexpr size_t kAdjLdsBudget = 64 * 1024;
 
@@ -99,10 +101,10 @@ TileBuild make_tiles(const cbct_geom *g, int TV)
             }
         }
     }
-    // Kernel box origin is floor(min) - 1 and it reads index floor(q) + 1;
-    // one more voxel on each side covers FP32 rounding of the corner lines.
-    tb.BQ = maxq + 5;
-    tb.BK = maxk + 5;
+    // The kernel stages [floor(min) - 1, floor(max) + 2] on each axis (reads
+    // reach floor(q) + 1); one more voxel covers FP32 rounding of the corners.
+    tb.BQ = maxq + 4;
+    tb.BK = maxk + 4;
     return tb;
 }
 
@@ -144,14 +146,14 @@ void plan_host(cbct_geom *g)
 {
     const cbct_geom_desc &d = g->desc;
 
-    // ---- forward tiles
+    // ---- forward tiles: the widest tiles whose box fits 64 x 32 voxels
     g->fwd = FwdPlan{};
     g->tiles.clear();
     TileBuild tb;
     int R = 0;
-    for (int r : {4, 2, 1}) {
+    for (int r : {8, 4, 2, 1}) {
         tb = make_tiles(g, 4 * r);
-        if (tb.BQ * tb.BK <= kMaxBox) {
+        if (tb.BQ <= kMaxBoxQ && tb.BK <= kMaxBoxK) {
             R = r;
             break;
         }

@@ -49,10 +49,15 @@ def cgls(geom: cbct.Geometry, y: torch.Tensor, iters: int, x0: torch.Tensor | No
     return x
 
 
-def opnorm(geom: cbct.Geometry, iters: int = 50, seed: int = 0) -> float:
-    """||A||_2 by power iteration on A^T A (FP32 operators, FP64 norms)."""
-    gen = torch.Generator(device="cpu").manual_seed(seed)
-    x = torch.randn(geom.vol_shape, generator=gen).to(geom.device)
+def opnorm(geom: cbct.Geometry, iters: int = 50, seed: int = 0,
+           x0: torch.Tensor | None = None) -> float:
+    """||A||_2 by power iteration on A^T A (FP32 operators, FP64 norms),
+    from x0 or a seeded Gaussian start."""
+    if x0 is None:
+        gen = torch.Generator(device="cpu").manual_seed(seed)
+        x = torch.randn(geom.vol_shape, generator=gen).to(geom.device)
+    else:
+        x = x0.detach().to(device=geom.device, dtype=torch.float32).contiguous()
     lam = 0.0
     for _ in range(iters):
         x = x / torch.linalg.vector_norm(x.double()).float()

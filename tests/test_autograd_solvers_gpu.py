@@ -171,9 +171,10 @@ def test_cgls_and_landweber_match_oracle(dev, oracle):
         _say(f"  CGLS iterate {k}: rel L2 {rel:.2e}")
         assert rel <= 1e-4
     assert xg.shape == tuple(W.vol_shape(g))
-    L = oracle.opnorm(g, iters=30)
-    Lg = solvers.opnorm(geo, iters=30)
-    assert abs(Lg - L) <= 1e-4 * L
+    x0 = W.rng(12).standard_normal(W.vol_shape(g))
+    L = oracle.opnorm(g, iters=30, x0=x0)
+    Lg = solvers.opnorm(geo, iters=30, x0=torch.tensor(x0, dtype=torch.float32, device="cuda"))
+    assert abs(Lg - L) <= 1e-5 * L
     omega = 1.0 / L ** 2
     xl = solvers.landweber(geo, yg, 5, omega).double().cpu().numpy()
     xr = oracle.landweber(g, y, 5, omega)
