@@ -16,6 +16,8 @@
 // constants.  Per voxel and column, the rows with non-zero weight form a run
 // that starts below the row where the ray crosses z = k - 1 and holds at
 // most NT rows; the taps use the clamped hat, so rows past the run add zero.
+// The window is stored column-major, so a run is consecutive LDS words read
+// two at a time with immediate offsets in a fully unrolled sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,31 +33,121 @@ constexpr int kBI = 8, kBJ = 8, kBK = 16, kV = 4;
 
 struct BrickArgs {
     DevGeom g;
-    int W, H, WS, NTmax;
+    int W, H, HS, NTmax;   // window columns and rows, LDS column stride (odd), taps
     int nbx, nby, nbz;
 };
 
 __device__ inline float sat(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
 // Fractional panel column of the ray through (x, y, .) and its source-panel
-// scale lambda (a point at height z lands at V = lambda z).
-__device__ inline void project_xy(const DevGeom &g, float c, float s, float x, float y,
-                                  float &u, float &lam)
+// scale lambda (a point at height z lands at V = lambda z).  Used only to
+// bound windows (every bound carries a margin), so approximate reciprocals
+// are enough.
+__device__ inline void project_xy(const DevGeom &g, float inv_du, float c, float s, float x,
+                                  float y, float &u, float &lam)
 {
     const float den = fmaf(c, x, fmaf(s, y, -g.sid));
-    lam = -g.sdd / den;
-    u = (lam * fmaf(-s, x, c * y) - g.off_u) / g.du + g.cu;
+    lam = -g.sdd * __builtin_amdgcn_rcpf(den);
+    u = fmaf(fmaf(lam, fmaf(-s, x, c * y), -g.off_u), inv_du, g.cu);
+}
+
+// Inputs of one angle's gather for one thread (voxel column ic, jc and the
+// kV voxels from k0 up).
+struct GatherIn {
+    const DevGeom &g;
+    const AngRec &ar;
+    const float *yt;
+    const float4 *cr;
+    int HS, U0, U1, V0, V1;
+    int ic, jc, k0;
+    float cxv, cyv, inv_du, inv_rvs;
+};
+
+// Accumulate one angle's contributions into acc, reading 2 NP taps per voxel
+// and column (rows past the non-zero run have zero weight).
+template <int NP>
+__device__ inline void gather_angle(const GatherIn &in, float (&acc)[kV])
+{
+    const DevGeom &g = in.g;
+    const AngRec &ar = in.ar;
+    const int HS = in.HS, U0 = in.U0, U1 = in.U1, V0 = in.V0, V1 = in.V1;
+    const int ic = in.ic, jc = in.jc, k0 = in.k0;
+    const float cxv = in.cxv, cyv = in.cyv, inv_du = in.inv_du, inv_rvs = in.inv_rvs;
+    const float *yt = in.yt;
+    const float4 *cr = in.cr;
+for (int cls = 0; cls < 2; ++cls) {
+        int c_lo, c_hi;   // this axis' columns, intersected below
+        float fp, qv;
+        float u1, u2, lam;
+        if (cls == 0) {   // x planes: plane i, in-plane j
+            if (ar.x_lo >= ar.x_hi)
+                continue;
+            c_lo = ar.x_lo;
+            c_hi = ar.x_hi - 1;
+            fp = (float)ic;
+            qv = (float)jc;
+            project_xy(g, inv_du, ar.c, ar.s, cxv, cyv - g.vy, u1, lam);
+            project_xy(g, inv_du, ar.c, ar.s, cxv, cyv + g.vy, u2, lam);
+        } else {          // y planes: plane j, in-plane i
+            if (ar.x_lo == 0 && ar.x_hi == g.nu)
+                continue;
+            c_lo = 0;
+            c_hi = g.nu - 1;
+            fp = (float)jc;
+            qv = (float)ic;
+            project_xy(g, inv_du, ar.c, ar.s, cxv - g.vx, cyv, u1, lam);
+            project_xy(g, inv_du, ar.c, ar.s, cxv + g.vx, cyv, u2, lam);
+        }
+        const int ul = max(max((int)floorf(fminf(u1, u2)), c_lo), U0);
+        const int uh = min(min((int)ceilf(fmaxf(u1, u2)), c_hi), U1);
+        for (int u = ul; u <= uh; ++u) {
+            if (cls == 1 && u >= ar.x_lo && u < ar.x_hi)
+                continue;   // those columns are sampled on x planes
+            const float4 C = cr[u - U0];
+            const float q = fmaf(fp, C.y, C.x);
+            const float wq = sat(1.0f - fabsf(q - qv));
+            const float t = fmaf(fp, C.w, C.z);
+            const float beta = t * g.rvs;
+            const float rt = __builtin_amdgcn_rcpf(t);
+            // row where the ray crosses z index kk - 1: vA + kk vB
+            const float vB = rt * inv_rvs;
+            const float vA = fmaf(fmaf(-1.0f - g.Kb, rt, -g.rv0), inv_rvs, g.cv);
+            const float *ycol = yt + (u - U0) * HS - V0;
+#pragma unroll
+            for (int n = 0; n < kV; ++n) {
+                const float kk = (float)(k0 + n);
+                // one row below that crossing, for rounding
+                const int vs = min(max((int)floorf(fmaf(kk, vB, vA)) - 1, V0), V1);
+                float s = fmaf(t, fmaf((float)vs - g.cv, g.rvs, g.rv0), g.Kb - kk);
+                const float *py = ycol + vs;
+                float csum = 0.0f;
+                float yv[2 * NP];
+#pragma unroll
+                for (int m = 0; m < 2 * NP; ++m)
+                    yv[m] = py[m];
+#pragma unroll
+                for (int m = 0; m < 2 * NP; ++m) {
+                    csum = fmaf(sat(1.0f - fabsf(s)), yv[m], csum);
+                    s += beta;
+                }
+                acc[n] = fmaf(wq, csum, acc[n]);
+            }
+        }
+    }
 }
 
 // Gather one brick (index b) of one channel: y is that channel's sinogram,
-// vol that channel's volume.  `lds` holds the panel window and column table.
+// vol that channel's volume.  `lds` holds the panel window, column-major
+// ([W][HS], HS odd so that a row of lanes writes distinct banks), and the
+// column table.
 template <class SS, class VS>
 __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__restrict__ y,
                              typename VS::T *__restrict__ vol, float *lds)
 {
     const DevGeom &g = A.g;
-    float *yt = lds;                                    // [H][WS] ds-weighted panel window
-    float4 *cr = (float4 *)(lds + (size_t)A.H * A.WS);  // [W] (pb, ps, t0, tau)
+    const int HS = A.HS;
+    float *yt = lds;                                    // [W][HS] ds-weighted panel window
+    float4 *cr = (float4 *)(lds + (size_t)A.W * HS);    // [W] (pb, ps, t0, tau)
 
     const int bx = b % A.nbx, by = (b / A.nbx) % A.nby, bz = b / (A.nbx * A.nby);
 
@@ -77,6 +169,7 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
     const float zs0 = g.oz + ((float)kz0 - 0.5f * (float)(g.nz - 1)) * g.vz - g.vz;
     const float zs1 = g.oz + ((float)kz1 - 0.5f * (float)(g.nz - 1)) * g.vz + g.vz;
 
+    const float inv_du = 1.0f / g.du, inv_dv = 1.0f / g.dv, inv_sdd = 1.0f / g.sdd;
     const float inv_rvs = 1.0f / g.rvs;
     float acc[kV] = {0.0f, 0.0f, 0.0f, 0.0f};
 
@@ -89,19 +182,19 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
         for (int q = 0; q < 4; ++q) {
             const float x = (q & 1) ? xs1 : xs0, yy = (q & 2) ? ys1 : ys0;
             float u, lam;
-            project_xy(g, ar.c, ar.s, x, yy, u, lam);
+            project_xy(g, inv_du, ar.c, ar.s, x, yy, u, lam);
             umin = fminf(umin, u);
             umax = fmaxf(umax, u);
-            const float va = (lam * zs0 - g.off_v) / g.dv + g.cv;
-            const float vb = (lam * zs1 - g.off_v) / g.dv + g.cv;
+            const float va = fmaf(fmaf(lam, zs0, -g.off_v), inv_dv, g.cv);
+            const float vb = fmaf(fmaf(lam, zs1, -g.off_v), inv_dv, g.cv);
             vmin = fminf(vmin, fminf(va, vb));
             vmax = fmaxf(vmax, fmaxf(va, vb));
-            tmin = fminf(tmin, (g.sid - fmaf(ar.c, x, ar.s * yy)) / g.sdd);
+            tmin = fminf(tmin, (g.sid - fmaf(ar.c, x, ar.s * yy)) * inv_sdd);
         }
         const int U0 = max((int)floorf(umin) - 1, 0);
         const int U1 = min(min((int)ceilf(umax) + 1, g.nu - 1), U0 + A.W - 1);
-        int NT = (int)floorf(2.0f / (tmin * g.rvs)) + 3;
-        NT = __builtin_amdgcn_readfirstlane(min(NT, A.NTmax));
+        int NT = adj_taps_rounded(min((int)floorf(2.0f / (tmin * g.rvs)) + 3, A.NTmax));
+        NT = __builtin_amdgcn_readfirstlane(NT);
         const int V0 = max((int)floorf(vmin) - 2, 0);
         const int V1 = min(min((int)ceilf(vmax) + 2, g.nv - 1), V0 + A.H - NT - 1);
         if (U0 > U1 || V0 > V1)
@@ -114,72 +207,34 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
             const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
             if (w == 0)
                 cr[uu] = make_float4(col.pb, col.ps, col.t0, col.tau);
+            const typename SS::T *ycol = y + (size_t)a * g.nv * g.nu + U0 + uu;
             for (int vv = w; vv < Hs; vv += 4) {
                 const int v = V0 + vv;
                 float val = 0.0f;
                 if (v <= V1) {
                     const float ds = col.dsf * sqrtf(col.n2 + g.rows[v].y);
-                    val = SS::ld(y, ((size_t)a * g.nv + v) * g.nu + U0 + uu) * ds;
+                    val = SS::ld(ycol, (size_t)v * g.nu) * ds;
                 }
-                yt[vv * A.WS + uu] = val;
+                yt[uu * HS + vv] = val;
             }
         }
         __syncthreads();
 
-        // ---- gather, once per sampling axis present at this angle
-#pragma unroll
-        for (int cls = 0; cls < 2; ++cls) {
-            int c_lo, c_hi;   // this axis' columns, intersected below
-            float fp, qv;
-            float u1, u2, lam;
-            if (cls == 0) {   // x planes: plane i, in-plane j
-                if (ar.x_lo >= ar.x_hi)
-                    continue;
-                c_lo = ar.x_lo;
-                c_hi = ar.x_hi - 1;
-                fp = (float)ic;
-                qv = (float)jc;
-                project_xy(g, ar.c, ar.s, cxv, cyv - g.vy, u1, lam);
-                project_xy(g, ar.c, ar.s, cxv, cyv + g.vy, u2, lam);
-            } else {          // y planes: plane j, in-plane i
-                if (ar.x_lo == 0 && ar.x_hi == g.nu)
-                    continue;
-                c_lo = 0;
-                c_hi = g.nu - 1;
-                fp = (float)jc;
-                qv = (float)ic;
-                project_xy(g, ar.c, ar.s, cxv - g.vx, cyv, u1, lam);
-                project_xy(g, ar.c, ar.s, cxv + g.vx, cyv, u2, lam);
-            }
-            int ul = max(max((int)floorf(fminf(u1, u2)), c_lo), U0);
-            int uh = min(min((int)ceilf(fmaxf(u1, u2)), c_hi), U1);
-            for (int u = ul; u <= uh; ++u) {
-                if (cls == 1 && u >= ar.x_lo && u < ar.x_hi)
-                    continue;   // those columns are sampled on x planes
-                const float4 C = cr[u - U0];
-                const float q = fmaf(fp, C.y, C.x);
-                const float wq = sat(1.0f - fabsf(q - qv));
-                const float t = fmaf(fp, C.w, C.z);
-                const float beta = t * g.rvs;
-                const float rt = __builtin_amdgcn_rcpf(t);
-                const int colo = u - U0;
-#pragma unroll
-                for (int n = 0; n < kV; ++n) {
-                    const float kk = (float)(k0 + n);
-                    // row where the ray crosses z index kk - 1, minus one for rounding
-                    const float vf = fmaf(fmaf(kk - 1.0f - g.Kb, rt, -g.rv0), inv_rvs, g.cv);
-                    const int vs = min(max((int)floorf(vf) - 1, V0), V1);
-                    const float vz = fmaf((float)vs - g.cv, g.rvs, g.rv0);
-                    float s = fmaf(t, vz, g.Kb - kk);
-                    const float *py = yt + (vs - V0) * A.WS + colo;
-                    float csum = 0.0f;
-                    for (int m = 0; m < NT; ++m) {
-                        csum = fmaf(sat(1.0f - fabsf(s)), py[m * A.WS], csum);
-                        s += beta;
-                    }
-                    acc[n] = fmaf(wq, csum, acc[n]);
-                }
-            }
+        // ---- gather with a compile-time tap count (NT rounded up to a
+        // supported even count; extra taps read zero weight)
+        const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, V1, ic, jc, k0, cxv, cyv, inv_du,
+                          inv_rvs};
+        switch (NT) {
+        case 4: gather_angle<2>(in, acc); break;
+        case 6: gather_angle<3>(in, acc); break;
+        case 8: gather_angle<4>(in, acc); break;
+        case 10: gather_angle<5>(in, acc); break;
+        case 12: gather_angle<6>(in, acc); break;
+        case 14: gather_angle<7>(in, acc); break;
+        case 16: gather_angle<8>(in, acc); break;
+        case 20: gather_angle<10>(in, acc); break;
+        case 24: gather_angle<12>(in, acc); break;
+        default: gather_angle<16>(in, acc); break;
         }
     }
 
@@ -239,12 +294,12 @@ adjoint_batch(BatchAdjArgs B)
 static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
 {
     return BrickArgs{g, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI, (g.ny + kBJ - 1) / kBJ,
-                     (g.nz + kBK - 1) / kBK};
+                     (g.nz + kBK - 1) / kBK};   // WS: column stride of the window
 }
 
 static size_t brick_lds(const AdjPlan &p)
 {
-    return ((size_t)p.H * p.WS + (size_t)p.W * 4) * sizeof(float);
+    return ((size_t)p.W * p.WS + (size_t)p.W * 4) * sizeof(float);
 }
 
 hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *sino,

@@ -66,12 +66,27 @@ struct FwdPlan {
     const TileRec *tiles = nullptr;   // device
 };
 
+// Row taps the adjoint reads per voxel and column: the needed count rounded
+// up to a count its kernel is instantiated for (4..16 even, 20, 24, 32).
+__host__ __device__ inline int adj_taps_rounded(int nt)
+{
+    if (nt <= 4)
+        return 4;
+    if (nt <= 16)
+        return nt + (nt & 1);
+    if (nt <= 20)
+        return 20;
+    if (nt <= 24)
+        return 24;
+    return 32;
+}
+
 // Adjoint plan: bricks of 8 x 8 x 16 voxels; per angle the brick's panel
 // footprint (at most W x H pixels, taps included) is staged in LDS.
 struct AdjPlan {
     bool ok = false;   // false: fall back to the one-thread-per-voxel kernel
     int W = 0, H = 0;  // footprint bounds (columns, rows)
-    int WS = 0;        // LDS row stride (floats)
+    int WS = 0;        // LDS column stride of the window (floats, odd)
     int NTmax = 0;     // largest row-tap count
 };
 

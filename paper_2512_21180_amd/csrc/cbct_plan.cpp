@@ -30,6 +30,7 @@ constexpr int kMaxBoxQ = 64;      // staged box: one 64-lane row per z index
 constexpr int kMaxBoxK = 32;      // and at most 32 rows
 constexpr int kBI = 8, kBJ = 8, kBK = 16;
 constexpr size_t kAdjLdsBudget = 64 * 1024;
+constexpr int kMaxTaps = 32;      // row taps per voxel and column in the adjoint
 
 struct TileBuild {
     std::vector<TileRec> tiles;
@@ -185,7 +186,7 @@ void plan_host(cbct_geom *g)
     }
     const double t_min = (d.sid_mm - R_sup) / d.sdd_mm;
     const double rvs = d.dv_mm / d.vz_mm;
-    const int NT = (int)std::floor(2.0 / (t_min * rvs)) + 3;
+    const int NT = adj_taps_rounded((int)std::floor(2.0 / (t_min * rvs)) + 3);
     int W = 0, H = 0;
     const int nbx = (d.nx + kBI - 1) / kBI, nby = (d.ny + kBJ - 1) / kBJ;
     const int nbz = (d.nz + kBK - 1) / kBK;
@@ -205,9 +206,11 @@ void plan_host(cbct_geom *g)
                 }
     W = std::min(W, d.nu + 4);
     H = std::min(H, d.nv + NT + 8);
-    int WS = (W + 3) & ~3;
-    size_t lds = (size_t)H * WS * sizeof(float) + (size_t)W * 4 * sizeof(float);
-    if (lds <= kAdjLdsBudget) {
+    // the window is stored column-major with an odd column stride, so a row
+    // of lanes writing consecutive columns hits distinct LDS banks
+    int WS = H | 1;
+    size_t lds = (size_t)W * WS * sizeof(float) + (size_t)W * 4 * sizeof(float);
+    if (lds <= kAdjLdsBudget && NT <= kMaxTaps) {
         g->adj.ok = true;
         g->adj.W = W;
         g->adj.H = H;

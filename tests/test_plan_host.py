@@ -177,6 +177,14 @@ def test_forward_box_indices_stay_in_lds(hosts, name):
     assert n > 0
 
 
+def taps_rounded(nt):
+    """Tap counts the adjoint kernel is instantiated for."""
+    for c in (4, 6, 8, 10, 12, 14, 16, 20, 24):
+        if nt <= c:
+            return c
+    return 32
+
+
 def _adj_brick_check(h, bx, by, bz, angles):
     g = h.g
     s = h.s
@@ -196,10 +204,12 @@ def _adj_brick_check(h, bx, by, bz, angles):
     def cz(k):
         return f32(s["oz"] + f32(f32(k) - f32(0.5) * f32(nz - 1)) * s["vz"])
 
+    inv_du, inv_dv = f32(f32(1.0) / s["du"]), f32(f32(1.0) / s["dv"])
+
     def proj(c_, s_, x, y):
         den = fma32(c_, x, fma32(s_, y, -s["sid"]))
-        lam = f32(-s["sdd"] / den)
-        u = f32(f32(f32(lam * fma32(-s_, x, f32(c_ * y))) - s["off_u"]) / s["du"]) + s["cu"]
+        lam = f32(-s["sdd"] * f32(f32(1.0) / den))
+        u = fma32(fma32(lam, fma32(-s_, x, f32(c_ * y)), -s["off_u"]), inv_du, s["cu"])
         return f32(u), lam
 
     checked = 0
@@ -215,17 +225,17 @@ def _adj_brick_check(h, bx, by, bz, angles):
                 u, lam = proj(c_, s_, x, y)
                 us.append(u)
                 for z in zs:
-                    vs_.append(f32(f32(f32(lam * z) - s["off_v"]) / s["dv"]) + s["cv"])
-                ts.append(f32(f32(s["sid"] - fma32(c_, x, f32(s_ * y))) / s["sdd"]))
+                    vs_.append(fma32(fma32(lam, z, -s["off_v"]), inv_dv, s["cv"]))
+                ts.append(f32(f32(s["sid"] - fma32(c_, x, f32(s_ * y))) * f32(f32(1.0) / s["sdd"])))
         U0 = max(int(np.floor(min(us))) - 1, 0)
         U1 = min(min(int(np.ceil(max(us))) + 1, nu - 1), U0 + W_ - 1)
-        NT = min(int(np.floor(f32(2.0) / f32(min(ts) * rvs))) + 3, NTmax)
+        NT = taps_rounded(min(int(np.floor(f32(2.0) / f32(min(ts) * rvs))) + 3, NTmax))
         V0 = max(int(np.floor(min(vs_))) - 2, 0)
         V1 = min(min(int(np.ceil(max(vs_))) + 2, nv - 1), V0 + H_ - NT - 1)
         if U0 > U1 or V0 > V1:
             # nothing of this brick may be visible at this angle
             continue
-        assert U1 - U0 + 1 <= W_ and V1 - V0 + 1 + NT <= H_ and W_ <= WS
+        assert U1 - U0 + 1 <= W_ and V1 - V0 + 1 + NT <= H_ and H_ <= WS and WS % 2 == 1
         for i in range(i0, i1 + 1):
             for j in range(j0, j1 + 1):
                 for cls in (0, 1):
@@ -258,7 +268,10 @@ def _adj_brick_check(h, bx, by, bz, angles):
                         kf = fma32(fp, (Cu[3] * Vz).astype(np.float32), fma32(Cu[2], Vz, Kb))
                         for kk in range(k0, k1 + 1):
                             rows_sup = np.nonzero(np.abs(kf.astype(np.float64) - kk) < 1.0)[0]
-                            vf = fma32(fma32(f32(kk - 1.0) - Kb, rt, -rv0), f32(1.0) / rvs, cv)
+                            inv_rvs = f32(f32(1.0) / rvs)
+                            vB = f32(rt * inv_rvs)
+                            vA = fma32(fma32(f32(-1.0) - Kb, rt, -rv0), inv_rvs, cv)
+                            vf = fma32(f32(kk), vB, vA)
                             vstart = min(max(int(np.floor(vf)) - 1, V0), V1)
                             assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)), \
                                 (a, i, j, kk, u, rows_sup, vstart, NT)
