@@ -1,0 +1,75 @@
+/*
+ * cbct_nn.h -- convolution kernels of libcbct.so for the learned primal-dual
+ * blocks (arXiv 2512.21180, Alg. 1: the dual block Gamma and primal block
+ * Lambda are stacks of 3x3x3 convolutions with LeakyReLU between them, their
+ * outputs added to half of the dual or primal latent; the output block is a
+ * 1x1x1 convolution).
+ *
+ * Activations inside a block are channel-last BF16 with exactly 16 channels:
+ * an array of S = nz*ny*nx positions (x fastest) of 16 bf16 values (unused
+ * channels are zero).  Latents and projector I/O stay channel-first FP32
+ * ([C][nz][ny][nx]); pack and the convolution epilogues convert.
+ *
+ * Weights of a 3x3x3 layer: bf16 [27][16 cout][16 cin], tap index
+ * t = (dz+1)*9 + (dy+1)*3 + (dx+1) for offsets dz, dy, dx in {-1, 0, 1};
+ * zero padding outside the grid ("same" convolution).  Arithmetic: BF16
+ * operands on the matrix cores (v_mfma_f32_16x16x32_bf16), FP32 accumulation.
+ *
+ * Every pointer is a device pointer owned by the caller except the host
+ * arrays of channel pointers; calls enqueue on `stream` (hipStream_t, NULL =
+ * null stream).  Results are deterministic (fixed reduction orders, no
+ * atomics).
+ */
+#ifndef CBCT_NN_H
+#define CBCT_NN_H
+
+#include "cbct.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* out[s][c] = bf16(scale[c] * in[c][s]) for c < n_in, 0 for n_in <= c < 16.
+ * in: host array of n_in device FP32 channel pointers (S elements each);
+ * scale: host array of n_in factors, or NULL for 1. */
+cbct_status cbct_pack16(size_t S, int n_in, const float *const *in, const float *scale,
+                        uint16_t *out, void *stream);
+
+/*
+ * One 3x3x3 convolution over a (nz, ny, nx) grid: acc[s][co] = bias[co] +
+ * sum_{t, ci} w[t][co][ci] x[s + offset(t)][ci].
+ *   transpose_w = 1 uses w[26 - t][ci][co] instead (the transposed, flipped
+ *   kernel: the data gradient of a convolution with w).
+ *   act_mask (optional, channel-last bf16 [S][16]): acc[s][co] *= 1 where
+ *   act_mask[s][co] > 0, else slope (the LeakyReLU derivative of the layer
+ *   whose output act_mask is).
+ *   act = 1 applies LeakyReLU(slope) to acc before the stores.
+ * Stores (either or both):
+ *   y_cl (channel-last bf16 [S][16]) <- acc;
+ *   y_cf[co][s] (host array of n_cf device FP32 channel pointers, co < n_cf)
+ *     <- acc (accumulate = 0) or += alpha * acc (accumulate = 1).
+ * bias may be NULL (zero).
+ */
+cbct_status cbct_conv3(int nz, int ny, int nx, const uint16_t *x, const uint16_t *w,
+                       int transpose_w, const float *bias, const uint16_t *act_mask, int act,
+                       float slope, uint16_t *y_cl, int n_cf, float *const *y_cf, int accumulate,
+                       float alpha, void *stream);
+
+/* Workspace cells (FP32) cbct_conv3_wgrad needs for a grid of S positions. */
+size_t cbct_conv3_wgrad_workspace(size_t S);
+
+/*
+ * Weight and bias gradients of a 3x3x3 convolution with input x and output
+ * gradient dy (both channel-last bf16 [S][16]):
+ *   dw[t][co][ci] = sum_s dy[s][co] x[s + offset(t)][ci],  db[co] = sum_s dy[s][co]
+ * (FP32, overwritten; db may be NULL).  Blocked partial sums in a fixed order
+ * in ws, then one ordered reduction.
+ */
+cbct_status cbct_conv3_wgrad(int nz, int ny, int nx, const uint16_t *x, const uint16_t *dy,
+                             float *dw, float *db, float *ws, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBCT_NN_H */

@@ -340,3 +340,63 @@ def sim_gaussian(clean: np.ndarray, sigma: float, seed: int, stream: int = 0) ->
     out = np.zeros_like(cc)
     lib.orc_sim_gaussian(cc.size, _dp(cc), float(sigma), seed, stream, _dp(out))
     return out.reshape(np.shape(clean))
+
+
+# ---- 3x3x3 convolutions of the learned blocks (Alg. 1, dual/primal blocks) ----
+#
+# Plain FP64 definitions, zero padding ("same" size), cross-correlation with
+# weight w[co][ci][kz][ky][kx] applied to x[ci][z + kz - 1][y + ky - 1][x + kx - 1].
+
+def _shift_views(D, H, W):
+    for kz in range(3):
+        for ky in range(3):
+            for kx in range(3):
+                yield kz, ky, kx
+
+
+def conv3(x: np.ndarray, w: np.ndarray, b=None) -> np.ndarray:
+    """y[co] = b[co] + sum_{ci,k} w[co,ci,k] x[ci, . + k - 1]  (FP64)."""
+    x = np.asarray(x, np.float64)
+    w = np.asarray(w, np.float64)
+    C, D, H, W = x.shape
+    xp = np.zeros((C, D + 2, H + 2, W + 2))
+    xp[:, 1:-1, 1:-1, 1:-1] = x
+    y = np.zeros((w.shape[0], D, H, W))
+    for kz, ky, kx in _shift_views(D, H, W):
+        patch = xp[:, kz:kz + D, ky:ky + H, kx:kx + W].reshape(C, -1)
+        y += (w[:, :, kz, ky, kx] @ patch).reshape(y.shape)
+    if b is not None:
+        y += np.asarray(b, np.float64)[:, None, None, None]
+    return y
+
+
+def conv3_dgrad(dy: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """dx[ci] = sum_{co,k} w[co,ci,k] dy[co, . - k + 1]: the transpose of conv3."""
+    dy = np.asarray(dy, np.float64)
+    w = np.asarray(w, np.float64)
+    Co, D, H, W = dy.shape
+    dxp = np.zeros((w.shape[1], D + 2, H + 2, W + 2))
+    for kz, ky, kx in _shift_views(D, H, W):
+        contrib = (w[:, :, kz, ky, kx].T @ dy.reshape(Co, -1)).reshape(-1, D, H, W)
+        dxp[:, kz:kz + D, ky:ky + H, kx:kx + W] += contrib
+    return dxp[:, 1:-1, 1:-1, 1:-1]
+
+
+def conv3_wgrad(x: np.ndarray, dy: np.ndarray):
+    """dw[co,ci,k] = sum_s dy[co,s] x[ci, s + k - 1];  db[co] = sum_s dy[co,s]."""
+    x = np.asarray(x, np.float64)
+    dy = np.asarray(dy, np.float64)
+    C, D, H, W = x.shape
+    Co = dy.shape[0]
+    xp = np.zeros((C, D + 2, H + 2, W + 2))
+    xp[:, 1:-1, 1:-1, 1:-1] = x
+    dw = np.zeros((Co, C, 3, 3, 3))
+    g = dy.reshape(Co, -1)
+    for kz, ky, kx in _shift_views(D, H, W):
+        patch = xp[:, kz:kz + D, ky:ky + H, kx:kx + W].reshape(C, -1)
+        dw[:, :, kz, ky, kx] = g @ patch.T
+    return dw, g.sum(axis=1)
+
+
+def leaky_relu(v, slope):
+    return np.where(v > 0, v, slope * v)

@@ -69,6 +69,13 @@ def _load():
     lib.cbct_philox_blocks.argtypes = [sz, u64, u32, vp, vp]
     lib.cbct_sim_poisson_log.argtypes = [sz, vp, vp, vp, dp, u64, u32, vp]
     lib.cbct_sim_gaussian.argtypes = [sz, vp, vp, dp, u64, u32, vp]
+    fl = ctypes.c_float
+    lib.cbct_pack16.argtypes = [sz, i32, ctypes.POINTER(vp), ctypes.POINTER(fl), vp, vp]
+    lib.cbct_conv3.argtypes = [i32, i32, i32, vp, vp, i32, vp, vp, i32, fl, vp, i32,
+                               ctypes.POINTER(vp), i32, fl, vp]
+    lib.cbct_conv3_wgrad_workspace.argtypes = [sz]
+    lib.cbct_conv3_wgrad_workspace.restype = sz
+    lib.cbct_conv3_wgrad.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.cbct_error_string.argtypes = [i32]
     lib.cbct_error_string.restype = ctypes.c_char_p
     lib.cbct_last_hip_error.argtypes = []
@@ -77,7 +84,8 @@ def _load():
                  "cbct_forward", "cbct_adjoint", "cbct_batch_forward", "cbct_batch_adjoint",
                  "cbct_geom_plan_info", "cbct_geom_create_host", "cbct_geom_table",
                  "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby",
-                 "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian"):
+                 "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian",
+                 "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -348,3 +356,87 @@ def sim_gaussian(clean: torch.Tensor, sigma: float, seed: int, stream_id: int = 
                                   float(sigma), seed, stream_id, _stream(clean.device)),
            "cbct_sim_gaussian")
     return out
+
+
+# ---- 3x3x3 convolutions (cbct_nn.h) ----------------------------------------
+
+def _bf16(t, what):
+    if not (t.is_cuda and t.dtype == torch.bfloat16 and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous bfloat16 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _cf_list(ts, what):
+    arr = (ctypes.c_void_p * max(1, len(ts)))()
+    for i, t in enumerate(ts):
+        arr[i] = _f32(t, f"{what}[{i}]").value
+    return arr
+
+
+def pack16(channels, out=None, scale=None) -> torch.Tensor:
+    """Channel-last bf16 [S, 16] from up to 16 channel-first FP32 tensors of S
+    elements each (remaining channels zero; optional per-channel scale)."""
+    S = channels[0].numel()
+    if any(c.numel() != S for c in channels) or len(channels) > 16:
+        raise ValueError("channel sizes differ or more than 16 channels")
+    if out is None:
+        out = torch.empty((S, 16), dtype=torch.bfloat16, device=channels[0].device)
+    sc = None
+    if scale is not None:
+        sc = (ctypes.c_float * len(channels))(*[float(v) for v in scale])
+    _check(_lib.cbct_pack16(S, len(channels), _cf_list(channels, "channels"), sc,
+                            _bf16(out, "out"), _stream(out.device)), "cbct_pack16")
+    return out
+
+
+def conv3(grid, x, w, bias=None, act=False, slope=0.01, mask=None, transpose_w=False,
+          y_cl=None, y_cf=(), accumulate=False, alpha=1.0):
+    """3x3x3 convolution on a (nz, ny, nx) grid of channel-last bf16 [S,16]
+    activations with bf16 weights [27,16,16]; stores into y_cl (bf16 [S,16])
+    and/or the channel-first FP32 tensors y_cf (see cbct_nn.h)."""
+    nz, ny, nx = grid
+    S = nz * ny * nx
+    if x.shape != (S, 16) or w.shape != (27, 16, 16):
+        raise ValueError("bad activation or weight shape")
+    if mask is not None and mask.shape != (S, 16):
+        raise ValueError("bad mask shape")
+    if y_cl is not None and y_cl.shape != (S, 16):
+        raise ValueError("bad output shape")
+    if bias is not None and not (bias.numel() >= 16):
+        raise ValueError("bias needs 16 entries")
+    for t in y_cf:
+        if t.numel() != S:
+            raise ValueError("channel-first output of the wrong size")
+    _check(_lib.cbct_conv3(nz, ny, nx, _bf16(x, "x"), _bf16(w, "w"), int(bool(transpose_w)),
+                           _f32(bias, "bias") if bias is not None else None,
+                           _bf16(mask, "mask") if mask is not None else None,
+                           int(bool(act)), float(slope),
+                           _bf16(y_cl, "y_cl") if y_cl is not None else None,
+                           len(y_cf), _cf_list(list(y_cf), "y_cf"), int(bool(accumulate)),
+                           float(alpha), _stream(x.device)), "cbct_conv3")
+    return y_cl
+
+
+def conv3_wgrad_workspace(S: int, device) -> torch.Tensor:
+    return torch.empty(int(_lib.cbct_conv3_wgrad_workspace(S)), dtype=torch.float32, device=device)
+
+
+def conv3_wgrad(grid, x, dy, dw, db, ws):
+    """dw [27,16,16] FP32 and db [16] FP32 (or None) of a 3x3x3 convolution."""
+    nz, ny, nx = grid
+    S = nz * ny * nx
+    if x.shape != (S, 16) or dy.shape != (S, 16) or dw.shape != (27, 16, 16):
+        raise ValueError("bad shapes")
+    _check(_lib.cbct_conv3_wgrad(nz, ny, nx, _bf16(x, "x"), _bf16(dy, "dy"), _f32(dw, "dw"),
+                                 _f32(db, "db") if db is not None else None, _f32(ws, "ws"),
+                                 _stream(x.device)), "cbct_conv3_wgrad")
+    return dw, db
+
+
+def conv3_weights(w: torch.Tensor) -> torch.Tensor:
+    """bf16 [27,16,16] device weights from a [cout, cin, 3, 3, 3] tensor
+    (cout, cin <= 16; tap t = 9 kz + 3 ky + kx; missing channels zero)."""
+    co, ci = w.shape[0], w.shape[1]
+    out = torch.zeros((27, 16, 16), dtype=torch.float32, device=w.device)
+    out[:, :co, :ci] = w.detach().float().permute(2, 3, 4, 0, 1).reshape(27, co, ci)
+    return out.to(torch.bfloat16).contiguous()
