@@ -68,6 +68,28 @@ size_t cbct_conv3_wgrad_workspace(size_t S);
 cbct_status cbct_conv3_wgrad(int nz, int ny, int nx, const uint16_t *x, const uint16_t *dy,
                              float *dw, float *db, float *ws, void *stream);
 
+/*
+ * 1x1x1 convolution of n_in channel-first FP32 channels (the output
+ * convolution of Alg. 1): v[s] = w[n_in] + sum_c w[c] in[c][s], accumulated
+ * in channel order with fused multiply-adds; out <- v (accumulate = 0) or
+ * out += alpha * v (accumulate = 1).  in: host array of n_in device
+ * pointers; w: device array of n_in + 1 floats (weights, then bias).
+ * out may not alias an input.  0 <= n_in <= 16.
+ */
+cbct_status cbct_conv1(size_t S, int n_in, const float *const *in, const float *w, float *out,
+                       int accumulate, float alpha, void *stream);
+
+/*
+ * Field-of-view tensor V of Alg. 1 (Sec. 2.6): for each voxel, the fraction
+ * of the n_angles projections in which it is visible, i.e. in which the ray
+ * from the source through the voxel centre meets the panel's sensitive area
+ * |u - off_u| <= nu du / 2, |v - off_v| <= nv dv / 2 (u, v: panel coordinates
+ * of that point, by central projection onto the panel plane).  Computed on
+ * the host in FP64 (works on host-only handles); out is a host array of
+ * nx ny nz floats, [nz][ny][nx].
+ */
+cbct_status cbct_fov_fraction(const cbct_geom *g, float *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -400,3 +400,148 @@ def conv3_wgrad(x: np.ndarray, dy: np.ndarray):
 
 def leaky_relu(v, slope):
     return np.where(v > 0, v, slope * v)
+
+
+# ---- field-of-view tensor V (Alg. 1 input; Sec. 2.6) -------------------------
+
+def fov_fraction(g: dict) -> np.ndarray:
+    """V[z][y][x]: fraction of the projections in which the ray from the
+    source through the voxel centre meets the panel's sensitive area
+    (|u - off_u| <= nu du / 2 and |v - off_v| <= nv dv / 2, u and v the
+    central projection of the centre onto the panel plane).  Brute force over
+    voxels and angles, FP64."""
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    o = g.get("origin", (0.0, 0.0, 0.0))
+    cx = o[0] + (np.arange(nx) - 0.5 * (nx - 1)) * g["vx"]
+    cy = o[1] + (np.arange(ny) - 0.5 * (ny - 1)) * g["vy"]
+    cz = o[2] + (np.arange(nz) - 0.5 * (nz - 1)) * g["vz"]
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    count = np.zeros(X.shape)
+    for th in angles_of(g):
+        c, s = np.cos(th), np.sin(th)
+        D = g["sid"] - (X * c + Y * s)            # depth along the central ray
+        u = g["sdd"] * (Y * c - X * s) / D
+        v = g["sdd"] * Z / D
+        vis = ((D > 0) & (np.abs(u - g["off_u"]) <= 0.5 * g["nu"] * g["du"])
+               & (np.abs(v - g["off_v"]) <= 0.5 * g["nv"] * g["dv"]))
+        count += vis
+    return count / g["n_angles"]
+
+
+# ---- single-scale learned primal-dual (Alg. 1, one resolution) --------------
+#
+# Per iteration i (states: primal latent f (8 volumes), dual latent h (8
+# sinograms), reconstruction x), with the normalised operators A/L and
+# normalised data y:
+#   d1, d2 = halves of h;  p1, p2 = halves of f
+#   d2 <- d2 + Gamma_i([A p2 / L, A x / L, d1, y])            (10 -> 4 channels)
+#   p2 <- p2 + Lambda_i([A^T d2 / L, p1, x, LW, V])          (11 -> 4 channels)
+#        with LW = A^T (A x / L - y) / L, the Landweber term
+#   x  <- x + o_i . [p1, p2] + o_i,bias                       (1x1x1 conv 8 -> 1)
+#   h, f <- Perm(h, rho_i), Perm(f, rho_i)    (new channel k = old channel rho_i[k])
+# Blocks: conv3 -> LeakyReLU -> conv3 -> LeakyReLU -> conv3.  Start: x = x0
+# (zero unless given), f = [x0, A^T y / L] x 4, h = [y] x 8.
+# params[i] = {"dual": [w1, b1, w2, b2, w3, b3], "primal": [...],
+#              "out": array of 9 (8 weights, bias), "perm": 8 indices}.
+
+def _block_fwd(z, p, slope):
+    w1, b1, w2, b2, w3, b3 = p
+    a1 = conv3(z, w1, b1)
+    h1 = leaky_relu(a1, slope)
+    a2 = conv3(h1, w2, b2)
+    h2 = leaky_relu(a2, slope)
+    return conv3(h2, w3, b3), (z, a1, h1, a2, h2)
+
+
+def _block_bwd(g_out, cache, p, slope):
+    w1, b1, w2, b2, w3, b3 = p
+    z, a1, h1, a2, h2 = cache
+    dw3, db3 = conv3_wgrad(h2, g_out)
+    g_a2 = conv3_dgrad(g_out, w3) * np.where(a2 > 0, 1.0, slope)
+    dw2, db2 = conv3_wgrad(h1, g_a2)
+    g_a1 = conv3_dgrad(g_a2, w2) * np.where(a1 > 0, 1.0, slope)
+    dw1, db1 = conv3_wgrad(z, g_a1)
+    return conv3_dgrad(g_a1, w1), [dw1, db1, dw2, db2, dw3, db3]
+
+
+def _lpd_iter(g, st, y, V, p, L, slope):
+    f, h, x = st
+    d1, d2 = h[:4], h[4:]
+    p1, p2 = f[:4], f[4:]
+    Ax = forward(g, x) / L
+    gin = np.stack([forward(g, c) / L for c in p2] + [Ax] + d1 + [y])
+    gout, cg = _block_fwd(gin, p["dual"], slope)
+    d2n = [d2[k] + gout[k] for k in range(4)]
+    LW = adjoint(g, Ax - y) / L
+    pin = np.stack([adjoint(g, c) / L for c in d2n] + p1 + [x, LW, V])
+    pout, cp = _block_fwd(pin, p["primal"], slope)
+    p2n = [p2[k] + pout[k] for k in range(4)]
+    fn, hn = p1 + p2n, d1 + d2n
+    o = np.asarray(p["out"], np.float64)
+    xn = x + sum(o[c] * fn[c] for c in range(8)) + o[8]
+    rho = list(p["perm"])
+    return ([fn[r] for r in rho], [hn[r] for r in rho], xn), (cg, cp, fn, hn, x)
+
+
+def lpd_init(g, y, L, x0=None):
+    x = np.zeros(vol_shape(g)) if x0 is None else np.asarray(x0, np.float64)
+    xbp = adjoint(g, y) / L
+    return ([x, xbp] * 4, [np.asarray(y, np.float64)] * 8, x)
+
+
+def lpd_forward(g: dict, y, V, params, L: float, slope: float = 0.01, x0=None):
+    """Reconstructions [x_1, ..., x_n] of the single-scale primal-dual net."""
+    st = lpd_init(g, y, L, x0)
+    out = []
+    for p in params:
+        st, _ = _lpd_iter(g, st, y, V, p, L, slope)
+        out.append(st[2])
+    return out
+
+
+def lpd_loss_grad(g: dict, y, V, params, L: float, x_true, wmask, slope: float = 0.01, x0=None):
+    """loss = sum_i 0.5 sum_p wmask_p (x_i,p - x_true,p)^2 over all iterates,
+    and its gradient with respect to every parameter (reverse mode with
+    stored activations, FP64).  Returns (loss, grads) with grads[i] =
+    {"dual": [...6], "primal": [...6], "out": array of 9}."""
+    st = lpd_init(g, y, L, x0)
+    caches, xs = [], []
+    for p in params:
+        st, c = _lpd_iter(g, st, y, V, p, L, slope)
+        caches.append(c)
+        xs.append(st[2])
+    loss = sum(0.5 * float(np.sum(wmask * (xi - x_true) ** 2)) for xi in xs)
+    zero_v = np.zeros(vol_shape(g))
+    zero_s = np.zeros(sino_shape(g))
+    gf = [zero_v] * 8
+    gh = [zero_s] * 8
+    gx = zero_v
+    grads = [None] * len(params)
+    for i in reversed(range(len(params))):
+        p = params[i]
+        cg, cp, fn, hn, x = caches[i]
+        rho = list(p["perm"])
+        gx = gx + wmask * (xs[i] - x_true)
+        gfn = [np.zeros_like(zero_v) for _ in range(8)]
+        ghn = [np.zeros_like(zero_s) for _ in range(8)]
+        for k, r in enumerate(rho):
+            gfn[r] = gfn[r] + gf[k]
+            ghn[r] = ghn[r] + gh[k]
+        o = np.asarray(p["out"], np.float64)
+        go = np.array([float(np.sum(fn[c] * gx)) for c in range(8)] + [float(np.sum(gx))])
+        for c in range(8):
+            gfn[c] = gfn[c] + o[c] * gx
+        g_p1, g_p2 = gfn[:4], gfn[4:]
+        g_d1, g_d2 = ghn[:4], ghn[4:]
+        g_pin, gprim = _block_bwd(np.stack(g_p2), cp, p["primal"], slope)
+        g_p1 = [g_p1[k] + g_pin[4 + k] for k in range(4)]
+        gx = gx + g_pin[8]
+        g_d2 = [g_d2[k] + forward(g, g_pin[k]) / L for k in range(4)]
+        gx = gx + adjoint(g, forward(g, g_pin[9]) / L) / L
+        g_gin, gdual = _block_bwd(np.stack(g_d2), cg, p["dual"], slope)
+        g_p2 = [g_p2[k] + adjoint(g, g_gin[k]) / L for k in range(4)]
+        gx = gx + adjoint(g, g_gin[4]) / L
+        g_d1 = [g_d1[k] + g_gin[5 + k] for k in range(4)]
+        gf, gh = g_p1 + g_p2, g_d1 + g_d2
+        grads[i] = {"dual": gdual, "primal": gprim, "out": go}
+    return loss, grads

@@ -76,6 +76,8 @@ def _load():
     lib.cbct_conv3_wgrad_workspace.argtypes = [sz]
     lib.cbct_conv3_wgrad_workspace.restype = sz
     lib.cbct_conv3_wgrad.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.cbct_conv1.argtypes = [sz, i32, ctypes.POINTER(vp), vp, vp, i32, fl, vp]
+    lib.cbct_fov_fraction.argtypes = [vp, vp]
     lib.cbct_error_string.argtypes = [i32]
     lib.cbct_error_string.restype = ctypes.c_char_p
     lib.cbct_last_hip_error.argtypes = []
@@ -85,7 +87,8 @@ def _load():
                  "cbct_geom_plan_info", "cbct_geom_create_host", "cbct_geom_table",
                  "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby",
                  "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian",
-                 "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad"):
+                 "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad", "cbct_conv1",
+                 "cbct_fov_fraction"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -440,3 +443,30 @@ def conv3_weights(w: torch.Tensor) -> torch.Tensor:
     out = torch.zeros((27, 16, 16), dtype=torch.float32, device=w.device)
     out[:, :co, :ci] = w.detach().float().permute(2, 3, 4, 0, 1).reshape(27, co, ci)
     return out.to(torch.bfloat16).contiguous()
+
+
+def conv1(channels, w, out, accumulate=False, alpha=1.0):
+    """out (+)= w[:n] . channels + w[n] (1x1x1 convolution; w a device FP32
+    tensor of n + 1 entries)."""
+    n = len(channels)
+    S = out.numel()
+    if any(c.numel() != S for c in channels) or w.numel() < n + 1:
+        raise ValueError("channel sizes differ or too few weights")
+    _check(_lib.cbct_conv1(S, n, _cf_list(channels, "channels"), _f32(w, "w"), _f32(out, "out"),
+                           int(bool(accumulate)), float(alpha), _stream(out.device)), "cbct_conv1")
+    return out
+
+
+def fov_fraction(g: dict):
+    """Field-of-view tensor V [nz][ny][nx] (numpy float32), computed on the
+    host by the library for geometry dict g."""
+    import numpy as np
+    h = ctypes.c_void_p()
+    d, _keep = make_desc(g)
+    _check(_lib.cbct_geom_create_host(ctypes.byref(d), ctypes.byref(h)), "cbct_geom_create_host")
+    try:
+        out = np.empty((g["nz"], g["ny"], g["nx"]), dtype=np.float32)
+        _check(_lib.cbct_fov_fraction(h, out.ctypes.data_as(ctypes.c_void_p)), "cbct_fov_fraction")
+    finally:
+        _lib.cbct_geom_destroy(h)
+    return out

@@ -278,6 +278,20 @@ __global__ void __launch_bounds__(kT) k_wgrad_reduce(const float *ws, float *dw,
         db[e - 27 * 256] = s;
 }
 
+// ---- conv1: 1x1x1 convolution of channel-first FP32 channels ---------------
+
+__global__ void __launch_bounds__(kT) k_conv1(size_t S, int n_in, CPtrList in, const float *w,
+                                              float *out, int accumulate, float alpha)
+{
+    const size_t s = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (s >= S)
+        return;
+    float v = w[n_in];
+    for (int c = 0; c < n_in; ++c)
+        v = fmaf(w[c], in.p[c][s], v);
+    out[s] = accumulate ? fmaf(alpha, v, out[s]) : v;
+}
+
 cbct_status nn_done(hipError_t e)
 {
     if (e == hipSuccess)
@@ -372,5 +386,25 @@ extern "C" cbct_status cbct_conv3_wgrad(int nz, int ny, int nx, const uint16_t *
     hipLaunchKernelGGL(k_wgrad, dim3(kWgBlocks), dim3(kT), 0, s, A);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((kWgCells + kT - 1) / kT), dim3(kT), 0, s,
                        (const float *)ws, dw, db);
+    return nn_done(hipGetLastError());
+}
+
+extern "C" cbct_status cbct_conv1(size_t S, int n_in, const float *const *in, const float *w,
+                                  float *out, int accumulate, float alpha, void *stream)
+{
+    if (!out || !w || (n_in > 0 && !in))
+        return CBCT_E_NULL;
+    if (n_in < 0 || n_in > kMaxCF)
+        return CBCT_E_SHAPE;
+    CPtrList L{};
+    for (int c = 0; c < n_in; ++c) {
+        if (!in[c])
+            return CBCT_E_NULL;
+        L.p[c] = in[c];
+    }
+    if (S == 0)
+        return CBCT_OK;
+    hipLaunchKernelGGL(k_conv1, dim3((unsigned)((S + kT - 1) / kT)), dim3(kT), 0,
+                       (hipStream_t)stream, S, n_in, L, w, out, accumulate ? 1 : 0, alpha);
     return nn_done(hipGetLastError());
 }
