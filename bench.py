@@ -29,6 +29,43 @@ OPS_PER_SAMPLE = 14
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
+# HBM traffic per launch of the projector kernels, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE runs (each scaled by what the counter reads for a 512 MiB
+# device copy), valid for the kernel sources whose hash it records.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "projector_c2_f32_hbm_traffic.json")
+KERNEL_SOURCES = ("cbct_adjoint.hip", "cbct_forward.hip", "cbct_internal.h", "cbct_storage.h",
+                  "cbct_plan.cpp", "cbct_geom.cpp", "cbct_api.cpp")
+
+
+def algorithmic_bytes(g):
+    """Compulsory HBM bytes of one FP32 launch: the input read once and the
+    output written once (volume and sinogram, 4 bytes per element)."""
+    return 4 * (g["nx"] * g["ny"] * g["nz"] + g["n_angles"] * g["nv"] * g["nu"])
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_21180_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """Bytes per launch of `kernel` from the recorded counter runs, or None
+    when there is no record or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["traffic_bytes"])
+
+
 def cpu_baseline(g, n_angles=72):
     """The FP64 oracle on the same geometry restricted to n_angles of its
     angles (every n/n_angles-th), forward then adjoint."""
@@ -141,7 +178,8 @@ def main():
             "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "TOP/s",
             "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(dom),
+            "algorithmic_bytes": algorithmic_bytes(g),
         },
     }
     if args.copy_calibration:

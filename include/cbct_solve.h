@@ -44,6 +44,12 @@ cbct_status cbct_xpay_ratio(size_t n, float *y, const float *x, const double *nu
 cbct_status cbct_axpby(size_t n, float *z, float alpha, const float *x, float beta,
                        const float *y, void *stream);
 
+/* g[i] = w[i] * (x[i] - t[i]): the gradient of the weighted squared error
+ * 0.5 sum_i w[i] (x[i] - t[i])^2 (the training loss of the learned
+ * primal-dual net, weights = field-of-view mask / its size). */
+cbct_status cbct_wresid(size_t n, float *g, const float *w, const float *x, const float *t,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

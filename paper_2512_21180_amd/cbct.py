@@ -76,6 +76,7 @@ def _load():
     lib.cbct_conv3_wgrad_workspace.argtypes = [sz]
     lib.cbct_conv3_wgrad_workspace.restype = sz
     lib.cbct_conv3_wgrad.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
+    lib.cbct_wresid.argtypes = [sz, vp, vp, vp, vp, vp]
     lib.cbct_conv1.argtypes = [sz, i32, ctypes.POINTER(vp), vp, vp, i32, fl, vp]
     lib.cbct_fov_fraction.argtypes = [vp, vp]
     lib.cbct_error_string.argtypes = [i32]
@@ -87,7 +88,7 @@ def _load():
                  "cbct_geom_plan_info", "cbct_geom_create_host", "cbct_geom_table",
                  "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby",
                  "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian",
-                 "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad", "cbct_conv1",
+                 "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad", "cbct_conv1", "cbct_wresid",
                  "cbct_fov_fraction"):
         getattr(lib, name).restype = i32
     return lib
@@ -326,6 +327,15 @@ def axpby(z, alpha, x, beta, y):
     _check(_lib.cbct_axpby(z.numel(), _f32(z, "z"), float(alpha), _f32(x, "x"), float(beta),
                            _f32(y, "y"), _stream(z.device)), "cbct_axpby")
     return z
+
+
+def wresid(g, w, x, t):
+    """g = w * (x - t) elementwise."""
+    if not (g.numel() == w.numel() == x.numel() == t.numel()):
+        raise ValueError("size mismatch")
+    _check(_lib.cbct_wresid(g.numel(), _f32(g, "g"), _f32(w, "w"), _f32(x, "x"), _f32(t, "t"),
+                            _stream(g.device)), "cbct_wresid")
+    return g
 
 
 # ---- simulator (cbct_sim.h) ------------------------------------------------

@@ -82,6 +82,14 @@ __global__ void __launch_bounds__(kT) axpby(size_t n, float *z, float alpha, con
         z[i] = fmaf(alpha, x[i], beta * y[i]);
 }
 
+__global__ void __launch_bounds__(kT) wresid(size_t n, float *g, const float *w, const float *x,
+                                             const float *t)
+{
+    const size_t stride = (size_t)gridDim.x * kT;
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += stride)
+        g[i] = w[i] * (x[i] - t[i]);
+}
+
 unsigned blocks_for(size_t n)
 {
     size_t b = (n + kT - 1) / kT;
@@ -141,5 +149,15 @@ extern "C" cbct_status cbct_axpby(size_t n, float *z, float alpha, const float *
         return CBCT_E_NULL;
     hipLaunchKernelGGL(axpby, dim3(blocks_for(n)), dim3(kT), 0, (hipStream_t)stream, n, z, alpha,
                        x, beta, y);
+    return done(hipGetLastError());
+}
+
+extern "C" cbct_status cbct_wresid(size_t n, float *g, const float *w, const float *x,
+                                   const float *t, void *stream)
+{
+    if (!g || !w || !x || !t)
+        return CBCT_E_NULL;
+    hipLaunchKernelGGL(wresid, dim3(blocks_for(n)), dim3(kT), 0, (hipStream_t)stream, n, g, w, x,
+                       t);
     return done(hipGetLastError());
 }
