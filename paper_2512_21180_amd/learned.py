@@ -237,13 +237,12 @@ class LearnedPD:
         P = _Prepared(self.net, zero_blocks)
         B = self._buf(False)
         f, h, x = self.init_state(y)
-        xa, xb = x, torch.empty_like(x)
+        pair = [x, torch.empty_like(x)]       # x_i and x_{i+1} alternate
         for i in range(self.net.n_iter):
-            f, h, xa = self._iteration(P, i, f, h, xa, y, B, xb)
-            xb = x if xa is not x else torch.empty_like(x)
+            f, h, x = self._iteration(P, i, f, h, pair[i % 2], y, B, pair[1 - i % 2])
             if callback is not None:
-                callback(i + 1, xa)
-        return xa
+                callback(i + 1, x)
+        return x
 
     # ---- training -----------------------------------------------------------
 
@@ -318,6 +317,7 @@ class LearnedPD:
                     cbct.axpby(gfn[4 + c], 1.0, gfn[4 + c], 1.0 / L, B.vG[c])
                 cbct.axpby(gx, 1.0, gx, 1.0 / L, B.vG[4])
                 f, h, gf, gh = fn, hn, gfn, ghn
+            self.rebuilt = (f, h)      # latents before the first iteration, rebuilt
             vals = cells.cpu().numpy()
             loss = 0.5 * float(sum(vals[2 * i] - vals[2 * i + 1] for i in range(n)))
             for i in range(n):
