@@ -66,6 +66,45 @@ def measured_traffic(kernel):
     return None if k is None else int(k["traffic_bytes"])
 
 
+def record_traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
+    """Write TRAFFIC_FILE from the counter_collection CSVs of a FETCH_SIZE and
+    a WRITE_SIZE run made with --copy-calibration."""
+    import csv
+
+    def per_kernel(path, counter):
+        out = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                key = ("copy" if "copyBuffer" in name else
+                       "adjoint" if "adjoint_brick" in name else
+                       "forward" if "forward_sweep" in name else None)
+                if key == "copy" and int(r["Grid_Size"]) < 4096:
+                    continue            # small staging copies, not the calibration copy
+                if key:
+                    out.setdefault(key, []).append(float(r["Counter_Value"]))
+        return out
+
+    fe, wr = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy_kib = 512 * 1024
+    ff = copy_kib / (sum(fe["copy"]) / len(fe["copy"]))
+    fw = copy_kib / (sum(wr["copy"]) / len(wr["copy"]))
+    rec = {"source_sha256": kernel_source_hash(), "command_fetch": fetch_cmd,
+           "command_write": write_cmd, "copy_bytes": copy_kib * 1024,
+           "copy_fetch_kib": fe["copy"], "copy_write_kib": wr["copy"],
+           "fetch_factor": round(ff, 5), "write_factor": round(fw, 5), "kernels": {}}
+    for k in ("adjoint", "forward"):
+        f_kib = sum(fe[k]) / len(fe[k]) * ff
+        w_kib = sum(wr[k]) / len(wr[k]) * fw
+        rec["kernels"][k] = {"fetch_kib": fe[k], "write_kib": wr[k],
+                             "traffic_bytes": int(round((f_kib + w_kib) * 1024))}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
+
+
 def cpu_baseline(g, n_angles=72):
     """The FP64 oracle on the same geometry restricted to n_angles of its
     angles (every n/n_angles-th), forward then adjoint."""
@@ -104,7 +143,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device-to-device copy (for counter calibration)")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record from two counter runs and exit (no GPU use)")
     args = ap.parse_args()
+    if args.record_traffic:
+        cmd = ("timeout -s KILL 120 rocprofv3 --pmc {c} -f csv -d {d} -o run -- python3 -u "
+               "bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration")
+        f_csv, w_csv = args.record_traffic
+        rec = record_traffic(f_csv, w_csv,
+                             cmd.format(c="FETCH_SIZE", d=os.path.dirname(f_csv)),
+                             cmd.format(c="WRITE_SIZE", d=os.path.dirname(w_csv)))
+        print(json.dumps({k: v["traffic_bytes"] for k, v in rec["kernels"].items()}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on a single GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)

@@ -135,7 +135,7 @@ cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
 /*
  * Batched forward over n >= 1 independent single-channel cases, each with
  * its own geometry handle and buffers (host arrays of n handles and n device
- * pointers), in one persistent launch.  Results are bitwise identical to n
+ * pointers), in one launch over all cases' work items.  Results are bitwise identical to n
  * separate cbct_forward calls.
  */
 cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,

@@ -104,7 +104,7 @@ static cbct_status check_batch(int n, const cbct_geom *const *g, const void *con
     return CBCT_OK;
 }
 
-// Batches run as persistent launches of up to kMaxBatch cases each; a case
+// Batches run as single launches over the work items of up to kMaxBatch cases; a case
 // whose plan fell back to the one-thread-per-output kernels is launched on
 // its own (same arithmetic, so the results are the same bits either way).
 extern "C" cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,

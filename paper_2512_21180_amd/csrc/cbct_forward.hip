@@ -189,7 +189,7 @@ forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
     sweep_tile<VS, SS>(A.g, T, A.R, vol + ch * nvox, sino + ch * nsino, lds);
 }
 
-// ---- batched forward: one persistent launch over (case, tile) items --------
+// ---- batched forward: one launch over all (case, tile) items ----------------
 
 struct FwdCase {
     DevGeom g;
@@ -210,17 +210,20 @@ __global__ void __launch_bounds__(kThreads)
 forward_batch(BatchFwdArgs B)
 {
     extern __shared__ float lds[];
-    for (int item = blockIdx.x; item < B.n_items; item += gridDim.x) {
-        int cs = 0;
-        while (cs + 1 < B.n_cases && item >= B.first[cs + 1])
-            ++cs;
-        const FwdCase &C = B.c[cs];
-        const TileRec T = C.tiles[item - B.first[cs]];
-        if (T.nu_t == 0)
-            continue;
-        sweep_tile<VS, SS>(C.g, T, C.R, (const typename VS::T *)C.vol, (typename SS::T *)C.sino,
-                           lds);
-    }
+    // one item per workgroup, XCD-contiguous as in forward_sweep; the
+    // hardware dispatcher balances the uneven items
+    const int per = gridDim.x >> 3;
+    const int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (item >= B.n_items)
+        return;
+    int cs = 0;
+    while (cs + 1 < B.n_cases && item >= B.first[cs + 1])
+        ++cs;
+    const FwdCase &C = B.c[cs];
+    const TileRec T = C.tiles[item - B.first[cs]];
+    if (T.nu_t == 0)
+        return;
+    sweep_tile<VS, SS>(C.g, T, C.R, (const typename VS::T *)C.vol, (typename SS::T *)C.sino, lds);
 }
 
 }  // namespace
@@ -258,8 +261,7 @@ hipError_t launch_forward_batch(int n, const cbct_geom *const *gs, const void *c
     }
     B.first[n] = items;
     B.n_items = items;
-    // persistent: enough workgroups to fill 256 CUs several times over
-    const int grid = std::min(items, 256 * 8);
+    const int grid = (items + 7) / 8 * 8;
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);

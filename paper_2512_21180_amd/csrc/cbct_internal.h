@@ -158,7 +158,8 @@ hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *
                                 cbct_dtype st, void *vol, cbct_dtype vt, int channels,
                                 hipStream_t s);
 
-// Batched launches: one persistent kernel over all cases' work items.  All
+// Batched launches: one kernel launch over all cases' work items (one item
+// per workgroup, the hardware dispatcher balances them).  All
 // cases must have tiled (forward) or bricked (adjoint) plans.
 constexpr int kMaxBatch = 16;
 hipError_t launch_forward_batch(int n, const cbct_geom *const *g, const void *const *vols,

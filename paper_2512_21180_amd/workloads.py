@@ -189,3 +189,23 @@ def phantom_c3(g: dict, seed: int):
                         body_radius=0.5 * w)
     body = dict(radius=0.5 * w, mu=0.02)
     return voxelise(g, el, body=body), el, body
+
+
+def slab(g: dict, nz: int, nv: int) -> dict:
+    """The central z-slab of nz voxel layers of g, with the nv panel rows
+    centred on it (same pitches, angles and offsets)."""
+    return dict(g, nz=int(nz), nv=int(nv))
+
+
+def phantom_c2_slab(g_slab: dict, seed: int, g_full: dict = None, n=50, body_diameter=300.0):
+    """A random z-section of a clinical-size phantom (body cylinder plus n
+    ellipsoids, as phantom_c2 on g_full), voxelised on the slab grid."""
+    g_full = C2 if g_full is None else g_full
+    el = ellipsoid_list(g_full, seed, count=(n, n), mu=(0.0, 0.04),
+                        body_radius=0.5 * body_diameter)
+    zr = 0.5 * (g_full["nz"] * g_full["vz"] - g_slab["nz"] * g_slab["vz"])
+    z0 = rng(seed + 1_000_003).uniform(-zr, zr)
+    for e in el:
+        e["centre"] = e["centre"] - np.array([0.0, 0.0, z0])
+    body = dict(radius=0.5 * body_diameter, mu=0.02)
+    return voxelise(g_slab, el, body=body)
