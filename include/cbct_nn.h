@@ -90,6 +90,27 @@ cbct_status cbct_conv1(size_t S, int n_in, const float *const *in, const float *
  */
 cbct_status cbct_fov_fraction(const cbct_geom *g, float *out);
 
+/*
+ * Resolution changes of the multiscale scheme (Alg. 1; r = 1/alpha in
+ * {1, 2, 4}; all arrays [n0][n1][n2] FP32, device, n2 fastest; sizes are the
+ * fine grid's and must be multiples of r; out may not alias in).
+ *   cbct_pool:      out[i][j][k] = scale * sum_{a,b,c<r} in[r i+a][r j+b][r k+c]
+ *                   (scale 1/r^3: Downsample, average pooling; scale 1: the
+ *                   adjoint of nearest upsampling)
+ *   cbct_projdown:  out[a][v][u] = scale * sum_{b,c<r} in[r a][r v+b][r u+c]
+ *                   (scale 1/r^2: ProjDown, which keeps every r-th projection
+ *                   and averages r x r pixel blocks)
+ *   cbct_upsample:  out[i][j][k] (+)= scale * in[i/r][j/r][k/r] over the fine
+ *                   grid (scale 1: nearest Upsample; scale 1/r^3: the adjoint
+ *                   of average pooling); accumulate = 1 adds to out.
+ */
+cbct_status cbct_pool(int r, int n0, int n1, int n2, const float *in, float *out, float scale,
+                      void *stream);
+cbct_status cbct_projdown(int r, int n0, int n1, int n2, const float *in, float *out,
+                          float scale, void *stream);
+cbct_status cbct_upsample(int r, int n0, int n1, int n2, const float *in, float *out,
+                          float scale, int accumulate, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

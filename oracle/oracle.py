@@ -428,21 +428,58 @@ def fov_fraction(g: dict) -> np.ndarray:
     return count / g["n_angles"]
 
 
-# ---- single-scale learned primal-dual (Alg. 1, one resolution) --------------
+# ---- learned primal-dual net (Alg. 1) ----------------------------------------
 #
-# Per iteration i (states: primal latent f (8 volumes), dual latent h (8
-# sinograms), reconstruction x), with the normalised operators A/L and
-# normalised data y:
+# Per iteration i at resolution 1/r_i (r_i in {1, 2, 4}, non-increasing), with
+# primal latent f (8 volumes), dual latent h (8 sinograms) at that resolution,
+# the full-resolution reconstruction x, normalised operators A_r / L of the
+# scaled geometry (every r-th projection, voxels and pixels r times larger)
+# and normalised data y:
+#   xb = Downsample_r(x) (average pooling);  yb = ProjDown_r(y);  Vb = Downsample_r(V)
 #   d1, d2 = halves of h;  p1, p2 = halves of f
-#   d2 <- d2 + Gamma_i([A p2 / L, A x / L, d1, y])            (10 -> 4 channels)
-#   p2 <- p2 + Lambda_i([A^T d2 / L, p1, x, LW, V])          (11 -> 4 channels)
-#        with LW = A^T (A x / L - y) / L, the Landweber term
-#   x  <- x + o_i . [p1, p2] + o_i,bias                       (1x1x1 conv 8 -> 1)
+#   d2 <- d2 + Gamma_i([A_r p2 / L, A_r xb / L, d1, yb])       (10 -> 4 channels)
+#   p2 <- p2 + Lambda_i([A_r^T d2 / L, p1, xb, LW, Vb])       (11 -> 4 channels)
+#        with LW = A_r^T (A_r xb / L - yb) / L, the Landweber term
+#   x  <- x + Upsample_r(o_i . [p1, p2] + o_i,bias)             (1x1x1 conv 8 -> 1)
 #   h, f <- Perm(h, rho_i), Perm(f, rho_i)    (new channel k = old channel rho_i[k])
+#   then, if r_{i+1} < r_i, h and f are upsampled (nearest) by r_i / r_{i+1}.
 # Blocks: conv3 -> LeakyReLU -> conv3 -> LeakyReLU -> conv3.  Start: x = x0
-# (zero unless given), f = [x0, A^T y / L] x 4, h = [y] x 8.
+# (zero unless given), f = [Downsample(x0), Downsample(A^T y / L)] x 4,
+# h = [ProjDown(y)] x 8 at resolution 1/r_1.  One constant L for every scale
+# (so that A_r Downsample(x) / L is close to ProjDown(A x / L)).
 # params[i] = {"dual": [w1, b1, w2, b2, w3, b3], "primal": [...],
 #              "out": array of 9 (8 weights, bias), "perm": 8 indices}.
+
+def scaled_geometry(g: dict, r: int) -> dict:
+    """The geometry of P_alpha, r = 1/alpha: every r-th projection, voxels
+    and pixels r times larger over the same volume and panel."""
+    if r == 1:
+        return g
+    h = dict(g)
+    h["angles"] = angles_of(g)[::r]
+    h["n_angles"] = len(h["angles"])
+    for n, d in (("nx", "vx"), ("ny", "vy"), ("nz", "vz"), ("nu", "du"), ("nv", "dv")):
+        h[n] = g[n] // r
+        h[d] = g[d] * r
+    return h
+
+
+def downsample(x: np.ndarray, r: int) -> np.ndarray:
+    """Average over r x r x r blocks."""
+    a, b, c = x.shape
+    return x.reshape(a // r, r, b // r, r, c // r, r).mean(axis=(1, 3, 5))
+
+
+def projdown(y: np.ndarray, r: int) -> np.ndarray:
+    """Every r-th projection, averaged over r x r pixel blocks."""
+    a, b, c = y.shape
+    return y[::r].reshape(a // r, b // r, r, c // r, r).mean(axis=(2, 4))
+
+
+def upsample(z: np.ndarray, r: int) -> np.ndarray:
+    """Nearest upsampling by r along all three axes."""
+    return np.repeat(np.repeat(np.repeat(z, r, axis=0), r, axis=1), r, axis=2)
+
 
 def _block_fwd(z, p, slope):
     w1, b1, w2, b2, w3, b3 = p
@@ -464,84 +501,114 @@ def _block_bwd(g_out, cache, p, slope):
     return conv3_dgrad(g_a1, w1), [dw1, db1, dw2, db2, dw3, db3]
 
 
-def _lpd_iter(g, st, y, V, p, L, slope):
-    f, h, x = st
+def _lpd_iter(g, f, h, xb, yb, Vb, p, L, slope):
+    """One coupling step at one resolution; returns the permuted latents,
+    the output convolution's value (at that resolution) and a cache."""
     d1, d2 = h[:4], h[4:]
     p1, p2 = f[:4], f[4:]
-    Ax = forward(g, x) / L
-    gin = np.stack([forward(g, c) / L for c in p2] + [Ax] + d1 + [y])
+    Ax = forward(g, xb) / L
+    gin = np.stack([forward(g, c) / L for c in p2] + [Ax] + d1 + [yb])
     gout, cg = _block_fwd(gin, p["dual"], slope)
     d2n = [d2[k] + gout[k] for k in range(4)]
-    LW = adjoint(g, Ax - y) / L
-    pin = np.stack([adjoint(g, c) / L for c in d2n] + p1 + [x, LW, V])
+    LW = adjoint(g, Ax - yb) / L
+    pin = np.stack([adjoint(g, c) / L for c in d2n] + p1 + [xb, LW, Vb])
     pout, cp = _block_fwd(pin, p["primal"], slope)
     p2n = [p2[k] + pout[k] for k in range(4)]
     fn, hn = p1 + p2n, d1 + d2n
     o = np.asarray(p["out"], np.float64)
-    xn = x + sum(o[c] * fn[c] for c in range(8)) + o[8]
+    c = sum(o[k] * fn[k] for k in range(8)) + o[8]
     rho = list(p["perm"])
-    return ([fn[r] for r in rho], [hn[r] for r in rho], xn), (cg, cp, fn, hn, x)
+    return [fn[k] for k in rho], [hn[k] for k in rho], c, (cg, cp, fn, hn)
 
 
-def lpd_init(g, y, L, x0=None):
+def _scales(params, scales):
+    sc = [1] * len(params) if scales is None else [int(r) for r in scales]
+    if len(sc) != len(params) or any(b > a for a, b in zip(sc, sc[1:])):
+        raise ValueError("one non-increasing scale per iteration")
+    return sc
+
+
+def lpd_init(g, y, L, x0=None, r=1):
     x = np.zeros(vol_shape(g)) if x0 is None else np.asarray(x0, np.float64)
-    xbp = adjoint(g, y) / L
-    return ([x, xbp] * 4, [np.asarray(y, np.float64)] * 8, x)
+    xbp = downsample(adjoint(g, y) / L, r)
+    xb = downsample(x, r)
+    yb = projdown(np.asarray(y, np.float64), r)
+    return [xb, xbp] * 4, [yb] * 8, x
 
 
-def lpd_forward(g: dict, y, V, params, L: float, slope: float = 0.01, x0=None):
-    """Reconstructions [x_1, ..., x_n] of the single-scale primal-dual net."""
-    st = lpd_init(g, y, L, x0)
-    out = []
-    for p in params:
-        st, _ = _lpd_iter(g, st, y, V, p, L, slope)
-        out.append(st[2])
-    return out
+def _lpd_run(g, y, V, params, L, slope, x0, scales):
+    sc = _scales(params, scales)
+    f, h, x = lpd_init(g, y, L, x0, sc[0])
+    xs, caches = [], []
+    for i, p in enumerate(params):
+        r = sc[i]
+        gr = scaled_geometry(g, r)
+        f, h, c, cache = _lpd_iter(gr, f, h, downsample(x, r), projdown(y, r), downsample(V, r),
+                                   p, L, slope)
+        caches.append(cache)
+        x = x + upsample(c, r)
+        xs.append(x)
+        if i + 1 < len(params) and sc[i + 1] < r:
+            f = [upsample(z, r // sc[i + 1]) for z in f]
+            h = [upsample(z, r // sc[i + 1]) for z in h]
+    return xs, caches, sc
 
 
-def lpd_loss_grad(g: dict, y, V, params, L: float, x_true, wmask, slope: float = 0.01, x0=None):
+def lpd_forward(g: dict, y, V, params, L: float, slope: float = 0.01, x0=None, scales=None):
+    """Reconstructions [x_1, ..., x_n] (full resolution) of the net."""
+    return _lpd_run(g, np.asarray(y, np.float64), np.asarray(V, np.float64), params, L, slope,
+                    x0, scales)[0]
+
+
+def lpd_loss_grad(g: dict, y, V, params, L: float, x_true, wmask, slope: float = 0.01, x0=None,
+                  scales=None):
     """loss = sum_i 0.5 sum_p wmask_p (x_i,p - x_true,p)^2 over all iterates,
     and its gradient with respect to every parameter (reverse mode with
     stored activations, FP64).  Returns (loss, grads) with grads[i] =
     {"dual": [...6], "primal": [...6], "out": array of 9}."""
-    st = lpd_init(g, y, L, x0)
-    caches, xs = [], []
-    for p in params:
-        st, c = _lpd_iter(g, st, y, V, p, L, slope)
-        caches.append(c)
-        xs.append(st[2])
+    y = np.asarray(y, np.float64)
+    V = np.asarray(V, np.float64)
+    xs, caches, sc = _lpd_run(g, y, V, params, L, slope, x0, scales)
     loss = sum(0.5 * float(np.sum(wmask * (xi - x_true) ** 2)) for xi in xs)
-    zero_v = np.zeros(vol_shape(g))
-    zero_s = np.zeros(sino_shape(g))
-    gf = [zero_v] * 8
-    gh = [zero_s] * 8
-    gx = zero_v
-    grads = [None] * len(params)
-    for i in reversed(range(len(params))):
-        p = params[i]
-        cg, cp, fn, hn, x = caches[i]
-        rho = list(p["perm"])
+    n = len(params)
+    gf = gh = None
+    gx = np.zeros(vol_shape(g))
+    grads = [None] * n
+    for i in reversed(range(n)):
+        p, r = params[i], sc[i]
+        gr = scaled_geometry(g, r)
+        cg, cp, fn, hn = caches[i]
+        if gf is None:
+            gf = [np.zeros(vol_shape(gr))] * 8
+            gh = [np.zeros(sino_shape(gr))] * 8
+        elif sc[i + 1] < r:       # adjoint of the nearest upsampling: block sums
+            q = r // sc[i + 1]
+            gf = [downsample(z, q) * q ** 3 for z in gf]
+            gh = [downsample(z, q) * q ** 3 for z in gh]
         gx = gx + wmask * (xs[i] - x_true)
-        gfn = [np.zeros_like(zero_v) for _ in range(8)]
-        ghn = [np.zeros_like(zero_s) for _ in range(8)]
-        for k, r in enumerate(rho):
-            gfn[r] = gfn[r] + gf[k]
-            ghn[r] = ghn[r] + gh[k]
+        rho = list(p["perm"])
+        gfn = [np.zeros(vol_shape(gr)) for _ in range(8)]
+        ghn = [np.zeros(sino_shape(gr)) for _ in range(8)]
+        for k, rr in enumerate(rho):
+            gfn[rr] = gfn[rr] + gf[k]
+            ghn[rr] = ghn[rr] + gh[k]
+        gc = downsample(gx, r) * r ** 3                      # adjoint of Upsample_r
         o = np.asarray(p["out"], np.float64)
-        go = np.array([float(np.sum(fn[c] * gx)) for c in range(8)] + [float(np.sum(gx))])
-        for c in range(8):
-            gfn[c] = gfn[c] + o[c] * gx
+        go = np.array([float(np.sum(fn[k] * gc)) for k in range(8)] + [float(np.sum(gc))])
+        for k in range(8):
+            gfn[k] = gfn[k] + o[k] * gc
         g_p1, g_p2 = gfn[:4], gfn[4:]
         g_d1, g_d2 = ghn[:4], ghn[4:]
         g_pin, gprim = _block_bwd(np.stack(g_p2), cp, p["primal"], slope)
         g_p1 = [g_p1[k] + g_pin[4 + k] for k in range(4)]
-        gx = gx + g_pin[8]
-        g_d2 = [g_d2[k] + forward(g, g_pin[k]) / L for k in range(4)]
-        gx = gx + adjoint(g, forward(g, g_pin[9]) / L) / L
+        gxb = g_pin[8].copy()
+        g_d2 = [g_d2[k] + forward(gr, g_pin[k]) / L for k in range(4)]
+        gxb = gxb + adjoint(gr, forward(gr, g_pin[9]) / L) / L
         g_gin, gdual = _block_bwd(np.stack(g_d2), cg, p["dual"], slope)
-        g_p2 = [g_p2[k] + adjoint(g, g_gin[k]) / L for k in range(4)]
-        gx = gx + adjoint(g, g_gin[4]) / L
+        g_p2 = [g_p2[k] + adjoint(gr, g_gin[k]) / L for k in range(4)]
+        gxb = gxb + adjoint(gr, g_gin[4]) / L
         g_d1 = [g_d1[k] + g_gin[5 + k] for k in range(4)]
+        gx = gx + upsample(gxb, r) / r ** 3                  # adjoint of Downsample_r
         gf, gh = g_p1 + g_p2, g_d1 + g_d2
         grads[i] = {"dual": gdual, "primal": gprim, "out": go}
     return loss, grads

@@ -77,6 +77,9 @@ def _load():
     lib.cbct_conv3_wgrad_workspace.restype = sz
     lib.cbct_conv3_wgrad.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp]
     lib.cbct_wresid.argtypes = [sz, vp, vp, vp, vp, vp]
+    lib.cbct_pool.argtypes = [i32, i32, i32, i32, vp, vp, fl, vp]
+    lib.cbct_projdown.argtypes = [i32, i32, i32, i32, vp, vp, fl, vp]
+    lib.cbct_upsample.argtypes = [i32, i32, i32, i32, vp, vp, fl, i32, vp]
     lib.cbct_conv1.argtypes = [sz, i32, ctypes.POINTER(vp), vp, vp, i32, fl, vp]
     lib.cbct_fov_fraction.argtypes = [vp, vp]
     lib.cbct_error_string.argtypes = [i32]
@@ -89,6 +92,7 @@ def _load():
                  "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby",
                  "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian",
                  "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad", "cbct_conv1", "cbct_wresid",
+                 "cbct_pool", "cbct_projdown", "cbct_upsample",
                  "cbct_fov_fraction"):
         getattr(lib, name).restype = i32
     return lib
@@ -479,4 +483,48 @@ def fov_fraction(g: dict):
         _check(_lib.cbct_fov_fraction(h, out.ctypes.data_as(ctypes.c_void_p)), "cbct_fov_fraction")
     finally:
         _lib.cbct_geom_destroy(h)
+    return out
+
+
+# ---- resolution changes (multiscale scheme) ---------------------------------
+
+def _fine_dims(t, r):
+    if t.dim() != 3 or any(d % r for d in t.shape):
+        raise ValueError("need a 3-D tensor with sizes divisible by r")
+    return tuple(int(d) for d in t.shape)
+
+
+def pool(x, r, out=None, scale=None):
+    """Block sums over r^3 blocks times scale (default 1/r^3: average pooling)."""
+    n0, n1, n2 = _fine_dims(x, r)
+    if out is None:
+        out = torch.empty((n0 // r, n1 // r, n2 // r), dtype=torch.float32, device=x.device)
+    sc = 1.0 / r ** 3 if scale is None else scale
+    _check(_lib.cbct_pool(r, n0, n1, n2, _f32(x, "in"), _f32(out, "out"), float(sc),
+                          _stream(x.device)), "cbct_pool")
+    return out
+
+
+def projdown(y, r, out=None, scale=None):
+    """Every r-th projection, r x r pixel blocks summed times scale (default
+    1/r^2: averaged)."""
+    n0, n1, n2 = _fine_dims(y, r)
+    if out is None:
+        out = torch.empty((n0 // r, n1 // r, n2 // r), dtype=torch.float32, device=y.device)
+    sc = 1.0 / r ** 2 if scale is None else scale
+    _check(_lib.cbct_projdown(r, n0, n1, n2, _f32(y, "in"), _f32(out, "out"), float(sc),
+                              _stream(y.device)), "cbct_projdown")
+    return out
+
+
+def upsample(c, r, out=None, scale=1.0, accumulate=False):
+    """Nearest upsampling by r times scale into out (or added to it)."""
+    if out is None:
+        out = torch.empty(tuple(int(d) * r for d in c.shape), dtype=torch.float32,
+                          device=c.device)
+    n0, n1, n2 = _fine_dims(out, r)
+    if tuple(c.shape) != (n0 // r, n1 // r, n2 // r):
+        raise ValueError("coarse and fine shapes do not match")
+    _check(_lib.cbct_upsample(r, n0, n1, n2, _f32(c, "in"), _f32(out, "out"), float(scale),
+                              int(bool(accumulate)), _stream(c.device)), "cbct_upsample")
     return out

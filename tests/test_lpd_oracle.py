@@ -157,3 +157,67 @@ def test_gradient_matches_central_differences(oracle):
                 assert min(errs) <= 1e-6 * max(abs(an), 1e-3 * loss), (i, part, j, idx, errs, an)
                 checked += 1
     assert checked == 28
+
+
+def test_resampling_pins(oracle):
+    r = W.rng(21)
+    x = r.standard_normal((8, 4, 12))
+    z = r.standard_normal((4, 2, 6))
+    # average pooling and nearest upsampling are adjoint up to the factor r^3
+    assert abs(np.vdot(oracle.downsample(x, 2), z) * 8 - np.vdot(x, oracle.upsample(z, 2))) \
+        < 1e-12 * np.abs(x).sum()
+    # pooling preserves the mean and reproduces block-constant arrays
+    assert abs(oracle.downsample(x, 2).mean() - x.mean()) < 1e-14
+    assert np.allclose(oracle.downsample(oracle.upsample(z, 4), 4), z, rtol=1e-14, atol=0)
+    # ProjDown keeps every r-th projection and averages pixel blocks
+    y = r.standard_normal((6, 8, 8))
+    pd = oracle.projdown(y, 2)
+    assert pd.shape == (3, 4, 4)
+    assert abs(pd[1, 2, 3] - y[2, 4:6, 6:8].mean()) < 1e-15
+    # a scaled geometry keeps the volume, panel and orbit
+    g2 = oracle.scaled_geometry(TOY, 2)
+    assert g2["nx"] * g2["vx"] == TOY["nx"] * TOY["vx"]
+    assert g2["nu"] * g2["du"] == TOY["nu"] * TOY["du"]
+    assert np.allclose(g2["angles"], oracle.angles_of(TOY)[::2])
+    # line integrals are nearly resolution independent: A_2 of the pooled
+    # phantom is close to ProjDown(A x) (same ray family, coarser sampling)
+    xt = W.phantom_c1(TOY, 4)[0]
+    a = oracle.forward(g2, oracle.downsample(xt, 2))
+    b = oracle.projdown(oracle.forward(TOY, xt), 2)
+    assert np.linalg.norm(a - b) <= 0.15 * np.linalg.norm(b)
+
+
+def test_multiscale_gradient_matches_central_differences(oracle):
+    g, x_true, L, y_raw, V = _setup(oracle, seed=5)
+    y = y_raw / L
+    params = _random_params(3, 31, scale=0.1)
+    scales = [2, 2, 1]
+    wmask = (V >= 0.5) / max(1, int((V >= 0.5).sum()))
+    slope = 0.1
+    xt = x_true / 0.02
+    loss, grads = oracle.lpd_loss_grad(g, y, V, params, L, xt, wmask, slope=slope,
+                                       scales=scales)
+
+    def loss_of(ps):
+        return sum(0.5 * float(np.sum(wmask * (xi - xt) ** 2))
+                   for xi in oracle.lpd_forward(g, y, V, ps, L, slope=slope, scales=scales))
+
+    assert abs(loss_of(params) - loss) <= 1e-12 * loss
+    r = W.rng(32)
+    for i in range(3):
+        for part, j in (("dual", 0), ("primal", 2), ("primal", 5), ("out", None)):
+            arr = params[i][part] if j is None else params[i][part][j]
+            an_all = grads[i][part] if j is None else grads[i][part][j]
+            idx = tuple(int(r.integers(n)) for n in arr.shape)
+            an = float(an_all[idx])
+            errs = []
+            for rel_h in (1e-6, 1e-7, 1e-8):
+                h = rel_h * max(1.0, abs(float(arr[idx])))
+                old = float(arr[idx])
+                arr[idx] = old + h
+                lp = loss_of(params)
+                arr[idx] = old - h
+                lm = loss_of(params)
+                arr[idx] = old
+                errs.append(abs((lp - lm) / (2 * h) - an))
+            assert min(errs) <= 1e-6 * max(abs(an), 1e-3 * loss), (i, part, j, idx, errs, an)
