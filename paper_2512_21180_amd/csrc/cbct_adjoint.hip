@@ -98,8 +98,22 @@ for (int cls = 0; cls < 2; ++cls) {
             project_xy(g, inv_du, ar.c, ar.s, cxv - g.vx, cyv, u1, lam);
             project_xy(g, inv_du, ar.c, ar.s, cxv + g.vx, cyv, u2, lam);
         }
-        const int ul = max(max((int)floorf(fminf(u1, u2)), c_lo), U0);
-        const int uh = min(min((int)ceilf(fmaxf(u1, u2)), c_hi), U1);
+        int ul = max(max((int)floorf(fminf(u1, u2)), c_lo), U0);
+        int uh = min(min((int)ceilf(fmaxf(u1, u2)), c_hi), U1);
+        // The columns strictly between u1 and u2 have a non-zero in-plane
+        // weight; the floor and ceil columns usually have exactly zero
+        // weight: drop them when their own weight (computed as in the loop)
+        // is zero, so no non-zero term is ever skipped.
+        if (ul <= uh) {
+            const float4 C = cr[ul - U0];
+            if (fabsf(fmaf(fp, C.y, C.x) - qv) >= 1.0f)
+                ++ul;
+        }
+        if (ul <= uh) {
+            const float4 C = cr[uh - U0];
+            if (fabsf(fmaf(fp, C.y, C.x) - qv) >= 1.0f)
+                --uh;
+        }
         for (int u = ul; u <= uh; ++u) {
             if (cls == 1 && u >= ar.x_lo && u < ar.x_hi)
                 continue;   // those columns are sampled on x planes
@@ -170,6 +184,8 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
     const float zs1 = g.oz + ((float)kz1 - 0.5f * (float)(g.nz - 1)) * g.vz + g.vz;
 
     const float inv_du = 1.0f / g.du, inv_dv = 1.0f / g.dv, inv_sdd = 1.0f / g.sdd;
+    // z of this wave's first voxel layer (wave-uniform)
+    const float zc_w0 = g.oz + ((float)k0 - 0.5f * (float)(g.nz - 1)) * g.vz;
     const float inv_rvs = 1.0f / g.rvs;
     float acc[kV] = {0.0f, 0.0f, 0.0f, 0.0f};
 
@@ -178,6 +194,7 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
         const AngRec ar = g.angs[a];
         // ---- panel window of the brick (uniform)
         float umin = 1e30f, umax = -1e30f, vmin = 1e30f, vmax = -1e30f, tmin = 1e30f;
+        float lmin = 1e30f, lmax = -1e30f;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float x = (q & 1) ? xs1 : xs0, yy = (q & 2) ? ys1 : ys0;
@@ -185,6 +202,8 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
             project_xy(g, inv_du, ar.c, ar.s, x, yy, u, lam);
             umin = fminf(umin, u);
             umax = fmaxf(umax, u);
+            lmin = fminf(lmin, lam);
+            lmax = fmaxf(lmax, lam);
             const float va = fmaf(fmaf(lam, zs0, -g.off_v), inv_dv, g.cv);
             const float vb = fmaf(fmaf(lam, zs1, -g.off_v), inv_dv, g.cv);
             vmin = fminf(vmin, fminf(va, vb));
@@ -220,6 +239,18 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
         }
         __syncthreads();
 
+        // ---- this wave's four voxel layers (z of the voxel centres +- one
+        // pitch) land on rows [wv0, wv1] for every ray through the brick's
+        // box (lambda is extreme at the box corners); a wave whose rows miss
+        // the staged rows entirely has only zero weights and skips the angle
+        // (wave-uniform branch; one row of margin for rounding).
+        {
+            const float zl = zc_w0 - g.vz, zh = zc_w0 + (float)(kV - 1) * g.vz + g.vz;
+            const float wv0 = fmaf(fminf(lmin * zl, lmax * zl) - g.off_v, inv_dv, g.cv);
+            const float wv1 = fmaf(fmaxf(lmin * zh, lmax * zh) - g.off_v, inv_dv, g.cv);
+            if (wv1 < (float)V0 - 1.0f || wv0 > (float)V1 + 1.0f)
+                continue;
+        }
         // ---- gather with a compile-time tap count (NT rounded up to a
         // supported even count; extra taps read zero weight)
         const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, V1, ic, jc, k0, cxv, cyv, inv_du,

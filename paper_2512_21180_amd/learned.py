@@ -55,16 +55,21 @@ def _dw_to_param(dw: torch.Tensor, co: int, ci: int) -> torch.Tensor:
 
 
 class PDNet(torch.nn.Module):
-    """Parameters of the n-iteration net (FP32 masters) and its fixed
-    permutations."""
+    """Parameters of the n-iteration net (FP32 masters), its fixed
+    permutations and the resolution divisor r_i of every iteration
+    (Alg. 1: iteration i runs at resolution 1/r_i; 1 = full)."""
 
     DUAL_IN = 10
     PRIMAL_IN = 11
 
-    def __init__(self, n_iter: int = 8, seed: int = 0, width: int = 16):
+    def __init__(self, n_iter: int = 8, seed: int = 0, width: int = 16, scales=None):
         super().__init__()
         if width != 16:
             raise ValueError("the convolution kernels are built for 16 channels")
+        self.scales = [1] * n_iter if scales is None else [int(r) for r in scales]
+        if len(self.scales) != n_iter or any(r not in (1, 2, 4) for r in self.scales) or \
+                any(b > a for a, b in zip(self.scales, self.scales[1:])):
+            raise ValueError("one non-increasing scale in {1, 2, 4} per iteration")
         gen = torch.Generator().manual_seed(seed)
         rng = np.random.default_rng(seed)
         self.n_iter = n_iter
@@ -116,13 +121,37 @@ class _Prepared:
 
         self.dual = [blk(net.dual[i]) for i in range(net.n_iter)]
         self.primal = [blk(net.primal[i]) for i in range(net.n_iter)]
-        # conv1 weights [o_0..o_7, 1 (the previous x), bias]
+        # conv1 weights: [o_0..o_7, 1 (the previous x), bias] at full
+        # resolution, where x is a ninth input; [o_0..o_7, bias] otherwise
         self.out = []
         for i in range(net.n_iter):
             o = net.out[i].detach().float()
-            self.out.append(torch.cat([o[:8], torch.ones(1, device=dev), o[8:9]]).contiguous())
+            if net.scales[i] == 1:
+                self.out.append(torch.cat([o[:8], torch.ones(1, device=dev), o[8:9]]).contiguous())
+            else:
+                self.out.append(o.contiguous())
         self.out_host = [net.out[i].detach().double().cpu().numpy() for i in range(net.n_iter)]
         self.perms = [list(p) for p in net.perms]
+
+
+def scaled_geometry(g: dict, r: int) -> dict:
+    """Geometry of the operator at resolution 1/r (Alg. 1, P_alpha with
+    alpha = 1/r): every r-th projection, voxels and pixels r times larger,
+    same volume, panel and orbit."""
+    if r == 1:
+        return dict(g)
+    n = int(g["n_angles"])
+    ang = g.get("angles")
+    ang = (2.0 * np.pi * np.arange(n) / n) if ang is None else np.asarray(ang, np.float64)
+    h = dict(g)
+    h["angles"] = ang[::r].copy()
+    h["n_angles"] = int(h["angles"].size)
+    for nk, dk in (("nx", "vx"), ("ny", "vy"), ("nz", "vz"), ("nu", "du"), ("nv", "dv")):
+        if int(g[nk]) % r:
+            raise ValueError(f"{nk} = {g[nk]} is not divisible by {r}")
+        h[nk] = int(g[nk]) // r
+        h[dk] = float(g[dk]) * r
+    return h
 
 
 class _Buffers:
@@ -138,12 +167,15 @@ class _Buffers:
         self.sA = [torch.empty(ss, **f32) for _ in range(5)]     # A p2 (4), A x
         self.sR = torch.empty(ss, **f32)                         # A x / L - y
         self.vB = [torch.empty(vs, **f32) for _ in range(5)]     # A^T d2 (4), A^T r
+        self.vX = torch.empty(vs, **f32)                         # Downsample(x)
+        self.vC = torch.empty(vs, **f32)                         # output convolution
         nbf = 5 if train else 3
         self.act = [torch.empty((S, 16), dtype=torch.bfloat16, device=dev) for _ in range(nbf)]
         if train:
             self.sT = [torch.empty(ss, **f32) for _ in range(5)]
             self.vG = [torch.empty(vs, **f32) for _ in range(5)]
             self.vT = torch.empty(vs, **f32)
+            self.vGX = torch.empty(vs, **f32)                    # gradient of Downsample(x)
             self.ones = torch.ones(vs, **f32)
             self.wg_ws = cbct.conv3_wgrad_workspace(S, dev)
             self.dot_ws = cbct.dot_workspace(max(self.Sv, self.Ss), dev)
@@ -155,21 +187,29 @@ class _Buffers:
 
 
 class LearnedPD:
-    """The net bound to one geometry: inference and reversible training."""
+    """The net bound to one full-resolution geometry: inference and
+    reversible training, at the resolutions the net's scales name."""
 
     def __init__(self, net: PDNet, geo: cbct.Geometry, V: torch.Tensor, L: float):
         self.net = net
         self.geo = geo
         self.V = V.contiguous()
         self.L = float(L)
+        self.levels = {}
+        for r in sorted(set(net.scales)):
+            gr = geo if r == 1 else cbct.Geometry(scaled_geometry(geo.params, r), geo.device)
+            Vr = self.V if r == 1 else cbct.pool(self.V, r)
+            self.levels[r] = {"geo": gr, "V": Vr, "vgrid": tuple(gr.vol_shape),
+                              "sgrid": tuple(gr.sino_shape), "bufs": {}}
+        # kept for callers of the single-scale interface
         self.vgrid = tuple(geo.vol_shape)
         self.sgrid = tuple(geo.sino_shape)
-        self._bufs = {}
 
-    def _buf(self, train):
-        if train not in self._bufs:
-            self._bufs[train] = _Buffers(self.geo, train)
-        return self._bufs[train]
+    def _buf(self, r, train):
+        lv = self.levels[r]
+        if train not in lv["bufs"]:
+            lv["bufs"][train] = _Buffers(lv["geo"], train)
+        return lv["bufs"][train]
 
     # ---- blocks -------------------------------------------------------------
 
@@ -203,43 +243,73 @@ class LearnedPD:
 
     # ---- forward ------------------------------------------------------------
 
-    def init_state(self, y: torch.Tensor):
+    def _data(self, y):
+        """ProjDown(y) for every resolution the net uses."""
+        return {r: (y if r == 1 else cbct.projdown(y, r)) for r in self.levels}
+
+    def init_state(self, y: torch.Tensor, ys=None):
+        """Latents at the first iteration's resolution and x_0 = 0."""
         geo, L = self.geo, self.L
+        r0 = self.net.scales[0]
+        ys = self._data(y) if ys is None else ys
         xbp = cbct.adjoint(geo, y)
         cbct.axpby(xbp, 1.0 / L, xbp, 0.0, xbp)
+        if r0 != 1:
+            xbp = cbct.pool(xbp, r0)
         x = torch.zeros(geo.vol_shape, dtype=torch.float32, device=y.device)
         f = []
         for k in range(NCH):
-            f.append(torch.zeros_like(x) if k % 2 == 0 else xbp.clone())
-        h = [y.clone() for _ in range(NCH)]
+            f.append(torch.zeros_like(xbp) if k % 2 == 0 else xbp.clone())
+        h = [ys[r0].clone() for _ in range(NCH)]
         return f, h, x
 
-    def _iteration(self, P, i, f, h, x, y, B, x_out):
-        geo, L = self.geo, self.L
+    def _iteration(self, P, i, f, h, x, ys, x_out):
+        """One iteration: couplings at resolution 1/r_i, x_out = x + Up(conv1),
+        then the permutation.  Returns (f, h, x_out)."""
+        L = self.L
+        r = self.net.scales[i]
+        lv = self.levels[r]
+        geo, B, V, y = lv["geo"], self._buf(r, False), lv["V"], ys[r]
+        xb = x if r == 1 else cbct.pool(x, r, out=B.vX)
         d1, d2 = h[:4], h[4:]
         p1, p2 = f[:4], f[4:]
         if not P.zero_blocks:
-            cbct.batch_forward([geo] * 5, p2 + [x], outs=B.sA)
-            self._block_forward(self.sgrid, B.Ss, B.sA + d1 + [y], [1.0 / L] * 5 + [1.0] * 5,
+            cbct.batch_forward([geo] * 5, p2 + [xb], outs=B.sA)
+            self._block_forward(lv["sgrid"], B.Ss, B.sA + d1 + [y], [1.0 / L] * 5 + [1.0] * 5,
                                 P.dual[i], d2, 1.0, B)
             cbct.axpby(B.sR, 1.0 / L, B.sA[4], -1.0, y)
             cbct.batch_adjoint([geo] * 5, d2 + [B.sR], outs=B.vB)
-            self._block_forward(self.vgrid, B.Sv, B.vB[:4] + p1 + [x, B.vB[4], self.V],
+            self._block_forward(lv["vgrid"], B.Sv, B.vB[:4] + p1 + [xb, B.vB[4], V],
                                 [1.0 / L] * 4 + [1.0] * 5 + [1.0 / L, 1.0],
                                 P.primal[i], p2, 1.0, B)
-        cbct.conv1(p1 + p2 + [x], P.out[i], x_out)
+        if r == 1:
+            cbct.conv1(p1 + p2 + [x], P.out[i], x_out)
+        else:
+            cbct.conv1(p1 + p2, P.out[i], B.vC)
+            cbct.axpby(x_out, 1.0, x, 0.0, x)
+            cbct.upsample(B.vC, r, out=x_out, accumulate=True)
         rho = P.perms[i]
-        return [f[r] for r in rho], [h[r] for r in rho], x_out
+        return [f[k] for k in rho], [h[k] for k in rho], x_out
+
+    def _refine(self, i, f, h):
+        """Nearest upsampling of the latents to the next iteration's resolution."""
+        sc = self.net.scales
+        if i + 1 < len(sc) and sc[i + 1] < sc[i]:
+            q = sc[i] // sc[i + 1]
+            f = [cbct.upsample(z, q) for z in f]
+            h = [cbct.upsample(z, q) for z in h]
+        return f, h
 
     @torch.no_grad()
     def reconstruct(self, y: torch.Tensor, zero_blocks: bool = False, callback=None):
         """x_n for normalised data y; callback(i, x_i) after each iteration."""
         P = _Prepared(self.net, zero_blocks)
-        B = self._buf(False)
-        f, h, x = self.init_state(y)
+        ys = self._data(y)
+        f, h, x = self.init_state(y, ys)
         pair = [x, torch.empty_like(x)]       # x_i and x_{i+1} alternate
         for i in range(self.net.n_iter):
-            f, h, x = self._iteration(P, i, f, h, pair[i % 2], y, B, pair[1 - i % 2])
+            f, h, x = self._iteration(P, i, f, h, pair[i % 2], ys, pair[1 - i % 2])
+            f, h = self._refine(i, f, h)
             if callback is not None:
                 callback(i + 1, x)
         return x
@@ -249,73 +319,101 @@ class LearnedPD:
     def loss_and_grad(self, y: torch.Tensor, x_true: torch.Tensor, wmask: torch.Tensor) -> float:
         """loss = sum_i 0.5 sum_p wmask_p (x_i,p - x_true,p)^2 over the n
         iterates; fills .grad of every parameter.  Reversible: latents of
-        earlier iterations are rebuilt by inverting the couplings."""
-        net, geo, L = self.net, self.geo, self.L
+        earlier iterations are rebuilt by inverting the couplings (and the
+        nearest upsampling between resolutions, by block averages)."""
+        net, L = self.net, self.L
+        sc = net.scales
         P = _Prepared(net)
-        B = self._buf(True)
         dev = y.device
         with torch.no_grad():
-            f, h, x = self.init_state(y)
+            ys = self._data(y)
+            f, h, x = self.init_state(y, ys)
             xs = [x]
             for i in range(net.n_iter):
-                f, h, xn = self._iteration(P, i, f, h, xs[-1], y, B, torch.empty_like(x))
+                f, h, xn = self._iteration(P, i, f, h, xs[-1], ys, torch.empty_like(x))
+                f, h = self._refine(i, f, h)
                 xs.append(xn)
             n = net.n_iter
+            res = torch.empty_like(x)                 # weighted residual of an iterate
+            res_ws = cbct.dot_workspace(x.numel(), dev)
             cells = torch.zeros(2 * n + 9 * n, dtype=torch.float64, device=dev)
-            gf = [torch.zeros_like(x) for _ in range(NCH)]
-            gh = [torch.zeros_like(y) for _ in range(NCH)]
+            gf = gh = None
             gx = torch.zeros_like(x)
-            r = B.vT
             for i in reversed(range(n)):
+                r = sc[i]
+                lv = self.levels[r]
+                geo, B, V, yb = lv["geo"], self._buf(r, True), lv["V"], ys[r]
+                if gf is None:
+                    gf = [torch.zeros(geo.vol_shape, dtype=torch.float32, device=dev)
+                          for _ in range(NCH)]
+                    gh = [torch.zeros(geo.sino_shape, dtype=torch.float32, device=dev)
+                          for _ in range(NCH)]
+                elif sc[i + 1] < r:
+                    # back to this resolution: block averages undo the nearest
+                    # upsampling of the latents; block sums are its adjoint
+                    q = r // sc[i + 1]
+                    f = [cbct.pool(z, q) for z in f]
+                    h = [cbct.pool(z, q) for z in h]
+                    gf = [cbct.pool(z, q, scale=1.0) for z in gf]
+                    gh = [cbct.pool(z, q, scale=1.0) for z in gh]
                 # loss term of x_{i+1}
-                cbct.wresid(r, wmask, xs[i + 1], x_true)
-                cbct.dot(r, xs[i + 1], B.dot_ws, cells[2 * i:2 * i + 1])
-                cbct.dot(r, x_true, B.dot_ws, cells[2 * i + 1:2 * i + 2])
-                cbct.axpby(gx, 1.0, gx, 1.0, r)
+                cbct.wresid(res, wmask, xs[i + 1], x_true)
+                cbct.dot(res, xs[i + 1], res_ws, cells[2 * i:2 * i + 1])
+                cbct.dot(res, x_true, res_ws, cells[2 * i + 1:2 * i + 2])
+                cbct.axpby(gx, 1.0, gx, 1.0, res)
                 # undo the permutation (states and their gradients)
                 rho = P.perms[i]
                 fn, hn, gfn, ghn = [None] * NCH, [None] * NCH, [None] * NCH, [None] * NCH
                 for k, rr in enumerate(rho):
                     fn[rr], hn[rr], gfn[rr], ghn[rr] = f[k], h[k], gf[k], gh[k]
-                # output convolution x_{i+1} = x_i + o . fn + bias
+                # output convolution: x_{i+1} = x_i + Up_r(o . fn + bias)
+                gc = gx if r == 1 else cbct.pool(gx, r, out=B.vC, scale=1.0)
                 oc = cells[2 * n + 9 * i:2 * n + 9 * i + 9]
                 for c in range(NCH):
-                    cbct.dot(fn[c], gx, B.dot_ws, oc[c:c + 1])
-                cbct.dot(B.ones, gx, B.dot_ws, oc[8:9])
+                    cbct.dot(fn[c], gc, B.dot_ws, oc[c:c + 1])
+                cbct.dot(B.ones, gc, B.dot_ws, oc[8:9])
                 oh = P.out_host[i]
                 for c in range(NCH):
-                    cbct.axpby(gfn[c], 1.0, gfn[c], float(oh[c]), gx)
-                xi = xs[i]
+                    cbct.axpby(gfn[c], 1.0, gfn[c], float(oh[c]), gc)
+                # Downsample(x_i) and the buffer for its gradient
+                if r == 1:
+                    xb, gxb = xs[i], gx
+                else:
+                    xb = cbct.pool(xs[i], r, out=B.vX)
+                    gxb = B.vGX
+                    gxb.zero_()
                 p1, p2, d1, d2 = fn[:4], fn[4:], hn[:4], hn[4:]
                 # primal coupling: rebuild its input, invert, backpropagate
-                cbct.forward(geo, xi, out=B.sA[4])
-                cbct.axpby(B.sR, 1.0 / L, B.sA[4], -1.0, y)
+                cbct.forward(geo, xb, out=B.sA[4])
+                cbct.axpby(B.sR, 1.0 / L, B.sA[4], -1.0, yb)
                 cbct.batch_adjoint([geo] * 5, d2 + [B.sR], outs=B.vB)
-                self._block_forward(self.vgrid, B.Sv, B.vB[:4] + p1 + [xi, B.vB[4], self.V],
+                self._block_forward(lv["vgrid"], B.Sv, B.vB[:4] + p1 + [xb, B.vB[4], V],
                                     [1.0 / L] * 4 + [1.0] * 5 + [1.0 / L, 1.0],
                                     P.primal[i], p2, -1.0, B)
                 for t in B.vG:
                     t.zero_()
-                self._block_backward(self.vgrid, B.Sv, gfn[4:], P.primal[i],
-                                     B.vG[:4] + gfn[:4] + [gx, B.vG[4]], B, net.primal[i])
-                # d(A^T d2 / L): g_d2 += A g / L;  d(LW): g_x += A^T A g / L^2
+                self._block_backward(lv["vgrid"], B.Sv, gfn[4:], P.primal[i],
+                                     B.vG[:4] + gfn[:4] + [gxb, B.vG[4]], B, net.primal[i])
+                # d(A^T d2 / L): g_d2 += A g / L;  d(LW): g_xb += A^T A g / L^2
                 cbct.batch_forward([geo] * 5, B.vG, outs=B.sT)
                 for c in range(4):
                     cbct.axpby(ghn[4 + c], 1.0, ghn[4 + c], 1.0 / L, B.sT[c])
                 cbct.adjoint(geo, B.sT[4], out=B.vT)
-                cbct.axpby(gx, 1.0, gx, 1.0 / (L * L), B.vT)
+                cbct.axpby(gxb, 1.0, gxb, 1.0 / (L * L), B.vT)
                 # dual coupling
                 cbct.batch_forward([geo] * 4, p2, outs=B.sA[:4])
-                self._block_forward(self.sgrid, B.Ss, B.sA + d1 + [y], [1.0 / L] * 5 + [1.0] * 5,
+                self._block_forward(lv["sgrid"], B.Ss, B.sA + d1 + [yb], [1.0 / L] * 5 + [1.0] * 5,
                                     P.dual[i], d2, -1.0, B)
                 for t in B.sT:
                     t.zero_()
-                self._block_backward(self.sgrid, B.Ss, ghn[4:], P.dual[i], B.sT + ghn[:4], B,
+                self._block_backward(lv["sgrid"], B.Ss, ghn[4:], P.dual[i], B.sT + ghn[:4], B,
                                      net.dual[i])
                 cbct.batch_adjoint([geo] * 5, B.sT, outs=B.vG)
                 for c in range(4):
                     cbct.axpby(gfn[4 + c], 1.0, gfn[4 + c], 1.0 / L, B.vG[c])
-                cbct.axpby(gx, 1.0, gx, 1.0 / L, B.vG[4])
+                cbct.axpby(gxb, 1.0, gxb, 1.0 / L, B.vG[4])
+                if r != 1:       # adjoint of average pooling
+                    cbct.upsample(gxb, r, out=gx, scale=1.0 / r ** 3, accumulate=True)
                 f, h, gf, gh = fn, hn, gfn, ghn
             self.rebuilt = (f, h)      # latents before the first iteration, rebuilt
             vals = cells.cpu().numpy()
@@ -324,14 +422,3 @@ class LearnedPD:
                 net.out[i].grad = torch.tensor(vals[2 * n + 9 * i:2 * n + 9 * i + 9],
                                                dtype=torch.float32, device=dev)
         return loss
-
-    def latents_after(self, y: torch.Tensor):
-        """Forward pass keeping (f, h, x) after the last iteration (for
-        testing the coupling inverse)."""
-        P = _Prepared(self.net)
-        B = self._buf(False)
-        with torch.no_grad():
-            f, h, x = self.init_state(y)
-            for i in range(self.net.n_iter):
-                f, h, x = self._iteration(P, i, f, h, x, y, B, torch.empty_like(x))
-        return f, h, x

@@ -34,11 +34,14 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _setup(dev, oracle, n_iter=3, seed=0):
+SCALES = [None, (2, 2, 1)]
+
+
+def _setup(dev, oracle, n_iter=3, seed=0, scales=None):
     torch, cbct, learned = dev
     g = TOY
     geo = cbct.Geometry(g)
-    net = learned.PDNet(n_iter=n_iter, seed=seed).cuda()
+    net = learned.PDNet(n_iter=n_iter, seed=seed, scales=scales).cuda()
     with torch.no_grad():
         for p in net.parameters():
             if p.dim() == 5:
@@ -50,6 +53,29 @@ def _setup(dev, oracle, n_iter=3, seed=0):
     V = cbct.fov_fraction(g)
     model = learned.LearnedPD(net, geo, torch.tensor(V, device="cuda"), L)
     return g, geo, net, model, L, y, V, x_true
+
+
+def test_resampling_kernels(dev, oracle):
+    torch, cbct, _ = dev
+    _say("[learned] pool / projdown / upsample")
+    r = W.rng(9)
+    for shape, q in (((8, 12, 20), 2), ((16, 8, 24), 4), ((6, 10, 14), 2)):
+        a = r.standard_normal(shape).astype(np.float32)
+        t = torch.tensor(a, device="cuda")
+        got = cbct.pool(t, q).double().cpu().numpy()
+        assert np.allclose(got, oracle.downsample(a.astype(np.float64), q), rtol=1e-6, atol=1e-6)
+        got = cbct.projdown(t, q).double().cpu().numpy()
+        assert np.allclose(got, oracle.projdown(a.astype(np.float64), q), rtol=1e-6, atol=1e-6)
+        c = torch.tensor(r.standard_normal(tuple(n // q for n in shape)).astype(np.float32),
+                         device="cuda")
+        up = cbct.upsample(c, q).double().cpu().numpy()
+        assert np.array_equal(up, oracle.upsample(c.double().cpu().numpy(), q))
+        acc = t.clone()
+        cbct.upsample(c, q, out=acc, scale=0.5, accumulate=True)
+        ref = a.astype(np.float64) + 0.5 * oracle.upsample(c.double().cpu().numpy(), q)
+        assert np.allclose(acc.double().cpu().numpy(), ref, rtol=1e-6, atol=1e-6)
+    with pytest.raises(Exception):
+        cbct.pool(torch.zeros((6, 6, 5), device="cuda"), 2)
 
 
 def test_conv1_and_wresid(dev):
@@ -73,15 +99,16 @@ def test_conv1_and_wresid(dev):
     assert torch.equal(g, ch[0] * (ch[1] - ch[2]))
 
 
-def test_forward_matches_oracle(dev, oracle):
+@pytest.mark.parametrize("scales", SCALES)
+def test_forward_matches_oracle(dev, oracle, scales):
     torch, cbct, learned = dev
-    _say("[learned] forward vs oracle (toy, 3 iterations)")
-    g, geo, net, model, L, y, V, _ = _setup(dev, oracle)
+    _say(f"[learned] forward vs oracle (toy, 3 iterations, scales {scales})")
+    g, geo, net, model, L, y, V, _ = _setup(dev, oracle, scales=scales)
     xs = []
     model.reconstruct(torch.tensor(y, device="cuda"),
                       callback=lambda i, x: xs.append(x.double().cpu().numpy()))
     ref = oracle.lpd_forward(g, y.astype(np.float64), V.astype(np.float64),
-                             net.oracle_params(), L)
+                             net.oracle_params(), L, scales=scales)
     for i, (a, b) in enumerate(zip(xs, ref)):
         rel = np.linalg.norm(a - b) / np.linalg.norm(b)
         _say(f"  x_{i + 1}: rel L2 {rel:.2e}")
@@ -92,21 +119,24 @@ def test_forward_matches_oracle(dev, oracle):
     for p in ps:
         for part in ("dual", "primal"):
             p[part] = [np.zeros_like(a) for a in p[part]]
-    rz = oracle.lpd_forward(g, y.astype(np.float64), V.astype(np.float64), ps, L)[-1]
+    rz = oracle.lpd_forward(g, y.astype(np.float64), V.astype(np.float64), ps, L,
+                            scales=scales)[-1]
     assert np.linalg.norm(xz - rz) <= 1e-5 * np.linalg.norm(rz)
 
 
-def test_gradient_matches_oracle_and_rebuilds_latents(dev, oracle):
+@pytest.mark.parametrize("scales", SCALES)
+def test_gradient_matches_oracle_and_rebuilds_latents(dev, oracle, scales):
     torch, cbct, learned = dev
-    _say("[learned] reversible gradient vs oracle (toy, 3 iterations)")
-    g, geo, net, model, L, y, V, x_true = _setup(dev, oracle, seed=3)
+    _say(f"[learned] reversible gradient vs oracle (toy, 3 iterations, scales {scales})")
+    g, geo, net, model, L, y, V, x_true = _setup(dev, oracle, seed=3, scales=scales)
     fov = (V >= 0.5)
     wmask = (fov / fov.sum()).astype(np.float32)
     yt = torch.tensor(y, device="cuda")
     loss = model.loss_and_grad(yt, torch.tensor(x_true, dtype=torch.float32, device="cuda"),
                                torch.tensor(wmask, device="cuda"))
     rloss, rgr = oracle.lpd_loss_grad(g, y.astype(np.float64), V.astype(np.float64),
-                                      net.oracle_params(), L, x_true, wmask.astype(np.float64))
+                                      net.oracle_params(), L, x_true, wmask.astype(np.float64),
+                                      scales=scales)
     _say(f"  loss {loss:.6e} oracle {rloss:.6e}")
     assert abs(loss - rloss) <= 4e-3 * rloss
     worst = 0.0
