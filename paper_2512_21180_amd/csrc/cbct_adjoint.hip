@@ -30,6 +30,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kBI = 8, kBJ = 8, kBK = 16, kV = 4;
+constexpr int kSB = 8;   // rows per staging batch (loads in flight per thread)
 
 struct BrickArgs {
     DevGeom g;
@@ -222,19 +223,30 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
         const int Hs = V1 - V0 + 1 + NT;   // staged rows (rows past V1 are zero)
 
         __syncthreads();   // previous angle's readers are done
+        // Columns on lanes, rows on waves (stride 4).  The loads of kSB rows
+        // are issued before any of them is used, so their latencies overlap
+        // instead of adding up row after row.
         for (int uu = lane; uu < Wc; uu += 64) {
             const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
             if (w == 0)
                 cr[uu] = make_float4(col.pb, col.ps, col.t0, col.tau);
             const typename SS::T *ycol = y + (size_t)a * g.nv * g.nu + U0 + uu;
-            for (int vv = w; vv < Hs; vv += 4) {
-                const int v = V0 + vv;
-                float val = 0.0f;
-                if (v <= V1) {
-                    const float ds = col.dsf * sqrtf(col.n2 + g.rows[v].y);
-                    val = SS::ld(ycol, (size_t)v * g.nu) * ds;
+            float *dst = yt + uu * HS;
+            for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
+                float val[kSB], vsq[kSB];
+#pragma unroll
+                for (int j = 0; j < kSB; ++j) {
+                    const int v = V0 + vv0 + 4 * j;
+                    const bool live = v <= V1;   // rows V1+1 .. V0+Hs-1 are zero
+                    val[j] = live ? SS::ld(ycol, (size_t)v * g.nu) : 0.0f;
+                    vsq[j] = live ? g.rows[v].y : 0.0f;
                 }
-                yt[uu * HS + vv] = val;
+#pragma unroll
+                for (int j = 0; j < kSB; ++j) {
+                    const int vv = vv0 + 4 * j;
+                    if (vv < Hs)
+                        dst[vv] = val[j] * (col.dsf * sqrtf(col.n2 + vsq[j]));
+                }
             }
         }
         __syncthreads();

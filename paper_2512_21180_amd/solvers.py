@@ -9,6 +9,9 @@ the host.
 """
 from __future__ import annotations
 
+import math
+
+import numpy as np
 import torch
 
 from . import cbct
@@ -57,13 +60,21 @@ def opnorm(geom: cbct.Geometry, iters: int = 50, seed: int = 0,
         gen = torch.Generator(device="cpu").manual_seed(seed)
         x = torch.randn(geom.vol_shape, generator=gen).to(geom.device)
     else:
-        x = x0.detach().to(device=geom.device, dtype=torch.float32).contiguous()
+        x = x0.detach().to(device=geom.device, dtype=torch.float32).contiguous().clone()
+    ws = cbct.dot_workspace(max(x.numel(), int(np.prod(geom.sino_shape))), x.device)
+    cells = torch.zeros(2, dtype=torch.float64, device=x.device)
+    q = torch.empty(geom.sino_shape, dtype=torch.float32, device=x.device)
+    z = torch.empty_like(x)
     lam = 0.0
     for _ in range(iters):
-        x = x / torch.linalg.vector_norm(x.double()).float()
-        z = cbct.adjoint(geom, cbct.forward(geom, x))
-        lam = float(torch.sum(x.double() * z.double()))
-        x = z
+        cbct.dot(x, x, ws, cells[0:1])
+        inv = 1.0 / math.sqrt(float(cells[0]))
+        cbct.axpby(x, inv, x, 0.0, x)                 # x <- x / |x|
+        cbct.forward(geom, x, out=q)
+        cbct.adjoint(geom, q, out=z)
+        cbct.dot(x, z, ws, cells[1:2])                # Rayleigh quotient of A^T A
+        lam = float(cells[1])
+        x, z = z, x
     return lam ** 0.5
 
 
