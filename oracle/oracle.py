@@ -612,3 +612,107 @@ def lpd_loss_grad(g: dict, y, V, params, L: float, x_true, wmask, slope: float =
         gf, gh = g_p1 + g_p2, g_d1 + g_d2
         grads[i] = {"dual": gdual, "primal": gprim, "out": go}
     return loss, grads
+
+
+# ---- FDK with offset-detector redundancy weights (Alg. 1 initialisation) ----
+#
+# Feldkamp-Davis-Kress for a circular orbit and a flat panel (Feldkamp et al.,
+# JOSA A 1984), in coordinates scaled to the isocentre (R = sid, D = sdd,
+# u_i = u R / D, v_i = v R / D for panel coordinates u, v measured from the
+# foot of the central ray):
+#   1. p_w = w(u) * R / sqrt(R^2 + u_i^2 + v_i^2) * p
+#   2. q = p_w (*) h along u, h the band-limited ramp (Ram-Lak) at pitch
+#      du_i: h(0) = 1 / (4 du_i^2), h(n du_i) = -1 / (pi^2 n^2 du_i^2) for odd
+#      n, 0 for even n; the convolution sum is multiplied by du_i
+#   3. f(r) = sum over angles of dbeta * R^2 / U^2 * q(beta, u_i(r), v_i(r)),
+#      U = R - (x cos beta + y sin beta), u_i(r) = R (y cos - x sin) / U,
+#      v_i(r) = R z / U, q interpolated bilinearly between pixel centres
+#      (zero outside the panel); dbeta = 2 pi / n (a full uniform orbit).
+# Redundancy weight w: the conjugate of a ray at u is the ray at -u, so the
+# weights of a conjugate pair must add to one.  Centred panel: w = 1/2.
+# Offset panel covering [off - W/2, off + W/2] with off > 0: overlap
+# |u| <= Delta = W/2 - off gets w = sin^2(pi/4 (1 + u / Delta)) (smooth,
+# w(u) + w(-u) = 1; Wang, Med. Phys. 2002), w = 1 for u > Delta (measured
+# once per orbit), and no measured ray has u < -Delta.
+
+def fdk_weight_u(g: dict, u) -> np.ndarray:
+    """Redundancy weight w at panel coordinate u (mm from the central ray)."""
+    u = np.asarray(u, np.float64)
+    if g["off_u"] == 0.0:
+        return np.full(u.shape, 0.5)
+    delta = 0.5 * g["nu"] * g["du"] - abs(g["off_u"])
+    s = np.sign(g["off_u"])
+    t = np.clip(s * u / delta, -1.0, 1.0)
+    return np.where(s * u > delta, 1.0, np.sin(0.25 * np.pi * (1.0 + t)) ** 2)
+
+
+def fdk_weights(g: dict) -> np.ndarray:
+    """Redundancy weight w(u) of each panel column."""
+    return fdk_weight_u(g, g["off_u"] + (np.arange(g["nu"]) - 0.5 * (g["nu"] - 1)) * g["du"])
+
+
+def ramp_kernel(n: np.ndarray, pitch: float) -> np.ndarray:
+    """Ram-Lak kernel h(n pitch): 1 / (4 pitch^2) at 0, -1 / (pi^2 n^2 pitch^2)
+    at odd n, 0 at even n."""
+    n = np.asarray(n)
+    h = np.zeros(n.shape)
+    h[n == 0] = 0.25
+    odd = (n % 2) != 0
+    h[odd] = -1.0 / (np.pi ** 2 * n[odd].astype(float) ** 2)
+    return h / pitch ** 2
+
+
+def fdk_filter(g: dict, p: np.ndarray) -> np.ndarray:
+    """Steps 1-2: weighted, ramp-filtered projections q[angle][v][u]."""
+    R, D = g["sid"], g["sdd"]
+    u = g["off_u"] + (np.arange(g["nu"]) - 0.5 * (g["nu"] - 1)) * g["du"]
+    v = g["off_v"] + (np.arange(g["nv"]) - 0.5 * (g["nv"] - 1)) * g["dv"]
+    ui, vi = u * R / D, v * R / D
+    dui = g["du"] * R / D
+    pre = fdk_weights(g)[None, :] * R / np.sqrt(R * R + ui[None, :] ** 2 + vi[:, None] ** 2)
+    pw = np.asarray(p, np.float64) * pre[None, :, :]
+    h = ramp_kernel(np.arange(-(g["nu"] - 1), g["nu"]), dui)
+    q = np.empty_like(pw)
+    nu = g["nu"]
+    for a in range(pw.shape[0]):
+        for iv in range(pw.shape[1]):
+            q[a, iv] = np.convolve(pw[a, iv], h)[nu - 1:2 * nu - 1] * dui
+    return q
+
+
+def fdk_backproject(g: dict, q: np.ndarray) -> np.ndarray:
+    """Step 3: voxel-driven weighted backprojection of filtered projections."""
+    R, D = g["sid"], g["sdd"]
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    o = g.get("origin", (0.0, 0.0, 0.0))
+    cx = o[0] + (np.arange(nx) - 0.5 * (nx - 1)) * g["vx"]
+    cy = o[1] + (np.arange(ny) - 0.5 * (ny - 1)) * g["vy"]
+    cz = o[2] + (np.arange(nz) - 0.5 * (nz - 1)) * g["vz"]
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    f = np.zeros(X.shape)
+    ang = angles_of(g)
+    dbeta = 2.0 * np.pi / len(ang)
+    nu, nv = g["nu"], g["nv"]
+    for a, th in enumerate(ang):
+        c, s = np.cos(th), np.sin(th)
+        U = R - (X * c + Y * s)
+        u = D * (Y * c - X * s) / U            # panel coordinates (mm)
+        v = D * Z / U
+        fu = (u - g["off_u"]) / g["du"] + 0.5 * (nu - 1)
+        fv = (v - g["off_v"]) / g["dv"] + 0.5 * (nv - 1)
+        iu0, iv0 = np.floor(fu).astype(int), np.floor(fv).astype(int)
+        au, av = fu - iu0, fv - iv0
+        val = np.zeros(X.shape)
+        for du_, wu in ((0, 1.0 - au), (1, au)):
+            for dv_, wv in ((0, 1.0 - av), (1, av)):
+                iu, iv = iu0 + du_, iv0 + dv_
+                ok = (iu >= 0) & (iu < nu) & (iv >= 0) & (iv < nv)
+                val += np.where(ok, wu * wv * q[a, np.clip(iv, 0, nv - 1), np.clip(iu, 0, nu - 1)],
+                                0.0)
+        f += dbeta * (R * R) / (U * U) * val
+    return f
+
+
+def fdk(g: dict, p: np.ndarray) -> np.ndarray:
+    """FDK reconstruction [nz][ny][nx] from line integrals p[angle][v][u]."""
+    return fdk_backproject(g, fdk_filter(g, p))

@@ -80,6 +80,7 @@ def _load():
     lib.cbct_pool.argtypes = [i32, i32, i32, i32, vp, vp, fl, vp]
     lib.cbct_projdown.argtypes = [i32, i32, i32, i32, vp, vp, fl, vp]
     lib.cbct_upsample.argtypes = [i32, i32, i32, i32, vp, vp, fl, i32, vp]
+    lib.cbct_fdk.argtypes = [vp, vp, vp, vp, vp]
     lib.cbct_conv1.argtypes = [sz, i32, ctypes.POINTER(vp), vp, vp, i32, fl, vp]
     lib.cbct_fov_fraction.argtypes = [vp, vp]
     lib.cbct_error_string.argtypes = [i32]
@@ -92,7 +93,7 @@ def _load():
                  "cbct_dot", "cbct_axpy_ratio", "cbct_xpay_ratio", "cbct_axpby",
                  "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian",
                  "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad", "cbct_conv1", "cbct_wresid",
-                 "cbct_pool", "cbct_projdown", "cbct_upsample",
+                 "cbct_pool", "cbct_projdown", "cbct_upsample", "cbct_fdk",
                  "cbct_fov_fraction"):
         getattr(lib, name).restype = i32
     return lib
@@ -527,4 +528,19 @@ def upsample(c, r, out=None, scale=1.0, accumulate=False):
         raise ValueError("coarse and fine shapes do not match")
     _check(_lib.cbct_upsample(r, n0, n1, n2, _f32(c, "in"), _f32(out, "out"), float(scale),
                               int(bool(accumulate)), _stream(c.device)), "cbct_upsample")
+    return out
+
+
+def fdk(geom: Geometry, sino: torch.Tensor, out: torch.Tensor | None = None,
+        work: torch.Tensor | None = None) -> torch.Tensor:
+    """FDK reconstruction with offset-detector redundancy weights (FP32)."""
+    if tuple(sino.shape) != tuple(geom.sino_shape):
+        raise ValueError("sinogram shape does not match the geometry")
+    if out is None:
+        out = torch.empty(geom.vol_shape, dtype=torch.float32, device=sino.device)
+    if work is None:
+        work = torch.empty(geom.sino_shape, dtype=torch.float32, device=sino.device)
+    with torch.cuda.device(geom.device):
+        _check(_lib.cbct_fdk(geom.handle, _f32(sino, "sino"), _f32(work, "work"),
+                             _f32(out, "out"), _stream(geom.device)), "cbct_fdk")
     return out

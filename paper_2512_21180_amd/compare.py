@@ -11,7 +11,8 @@ noise at I0 photons per pixel.  For each phantom:
   the time at which each method's iterates first reach it (start: data
   resident in HBM; L and V are per-geometry constants computed once);
 * the net with every block zeroed (only the output convolutions act), to
-  show what the blocks contribute.
+  show what the blocks contribute, and FDK (the classic one-pass method and
+  the net's optional starting point).
 
 PSNR over the full field of view (voxels seen in at least half of the
 projections): 10 log10(max(x_true)^2 / mean((x - x_true)^2)) in units of
@@ -97,6 +98,9 @@ def main(argv=None):
         print(f"[compare]   CGLS best {max(ps_cg):.2f} dB at iteration "
               f"{int(np.argmax(ps_cg)) + 1} ({t_cg[int(np.argmax(ps_cg))]:.3f} s); "
               f"{K} iterations {t_cg[-1]:.3f} s", flush=True)
+        # FDK (offset-detector weights) on the same data: A x = L y
+        t_fdk = timed(lambda mark: (cbct.fdk(geo, y_cg), mark(1)), 1)[0]
+        ps_fdk = psnr(cbct.fdk(geo, y_cg), xt, peak)
         n = net.n_iter
         t_ln = timed(lambda mark: model.reconstruct(y, callback=lambda i, x: mark(i)), n)
         ps_ln = []
@@ -119,8 +123,10 @@ def main(argv=None):
              "learned_psnr_db": [round(v, 3) for v in ps_ln],
              "learned_time_s": [round(v, 4) for v in t_ln],
              "zero_block_psnr_db": [round(v, 3) for v in ps_zero],
+             "fdk_psnr_db": round(ps_fdk, 3), "fdk_time_s": round(t_fdk, 4),
              "cgls_time_to_target_s": first(ps_cg, t_cg),
              "learned_time_to_target_s": first(ps_ln, t_ln)}
+        print(f"[compare]   FDK {ps_fdk:.2f} dB ({t_fdk:.3f} s)", flush=True)
         print(f"[compare]   learned {ps_ln[-1]:.2f} dB after {n} iterations ({t_ln[-1]:.3f} s); "
               f"zero-block net {ps_zero[-1]:.2f} dB; time to {target:.2f} dB: CGLS "
               f"{r['cgls_time_to_target_s']} s, learned {r['learned_time_to_target_s']} s",
@@ -133,6 +139,8 @@ def main(argv=None):
         "learned_psnr_db_mean": round(float(np.mean([r["learned_psnr_db"][-1] for r in results])), 3),
         "zero_block_psnr_db_mean": round(float(np.mean([r["zero_block_psnr_db"][-1]
                                                           for r in results])), 3),
+        "fdk_psnr_db_mean": round(float(np.mean([r["fdk_psnr_db"] for r in results])), 3),
+        "net": {"iterations": net.n_iter, "scales": list(net.scales), "init": net.init},
         "results": results,
     }
     print(json.dumps({k: v for k, v in summary.items() if k != "results"}), flush=True)

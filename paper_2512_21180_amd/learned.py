@@ -15,7 +15,8 @@ Blocks Gamma and Lambda are conv3 -> LeakyReLU -> conv3 -> LeakyReLU -> conv3
 with 16 hidden channels (the paper's dual block has the same three-layer
 shape with 64 filters; its primal block is a P4-equivariant U-Net, here the
 same plain three-layer block).  V is the field-of-view fraction of Sec. 2.6.
-Start (x_0 = 0): f = [x_0, A^T y / L] x 4, h = [y] x 8.  The couplings are
+Start: x_0 = 0 or the FDK reconstruction (Alg. 1), f = [x_0, A^T y / L] x 4,
+h = [y] x 8.  The couplings are
 additive, so an iteration is inverted by recomputing the block and
 subtracting (Sec. 2.6: gradients without stored activations): training keeps
 only the latents of the last iteration and the reconstructions x_1..x_n
@@ -62,8 +63,12 @@ class PDNet(torch.nn.Module):
     DUAL_IN = 10
     PRIMAL_IN = 11
 
-    def __init__(self, n_iter: int = 8, seed: int = 0, width: int = 16, scales=None):
+    def __init__(self, n_iter: int = 8, seed: int = 0, width: int = 16, scales=None,
+                 init: str = "zero"):
         super().__init__()
+        if init not in ("zero", "fdk"):
+            raise ValueError("init is 'zero' or 'fdk'")
+        self.init = init
         if width != 16:
             raise ValueError("the convolution kernels are built for 16 channels")
         self.scales = [1] * n_iter if scales is None else [int(r) for r in scales]
@@ -248,7 +253,9 @@ class LearnedPD:
         return {r: (y if r == 1 else cbct.projdown(y, r)) for r in self.levels}
 
     def init_state(self, y: torch.Tensor, ys=None):
-        """Latents at the first iteration's resolution and x_0 = 0."""
+        """Latents at the first iteration's resolution and x_0 (zero, or the
+        FDK reconstruction of Alg. 1: since A x = L y for normalised data,
+        x_0 = L FDK(y))."""
         geo, L = self.geo, self.L
         r0 = self.net.scales[0]
         ys = self._data(y) if ys is None else ys
@@ -256,10 +263,16 @@ class LearnedPD:
         cbct.axpby(xbp, 1.0 / L, xbp, 0.0, xbp)
         if r0 != 1:
             xbp = cbct.pool(xbp, r0)
-        x = torch.zeros(geo.vol_shape, dtype=torch.float32, device=y.device)
+        if self.net.init == "fdk":
+            x = cbct.fdk(geo, y)
+            cbct.axpby(x, L, x, 0.0, x)
+            xb = x if r0 == 1 else cbct.pool(x, r0)
+        else:
+            x = torch.zeros(geo.vol_shape, dtype=torch.float32, device=y.device)
+            xb = torch.zeros_like(xbp)
         f = []
         for k in range(NCH):
-            f.append(torch.zeros_like(xbp) if k % 2 == 0 else xbp.clone())
+            f.append(xb.clone() if k % 2 == 0 else xbp.clone())
         h = [ys[r0].clone() for _ in range(NCH)]
         return f, h, x
 

@@ -57,6 +57,7 @@ def save(net: learned.PDNet, path: str, meta: dict):
     state["perms"] = torch.tensor(net.perms, dtype=torch.int64)
     state["meta_n_iter"] = torch.tensor(net.n_iter)
     state["meta_scales"] = torch.tensor(net.scales, dtype=torch.int64)
+    state["meta_fdk_init"] = torch.tensor(1 if net.init == "fdk" else 0)
     torch.save(state, path)
 
 
@@ -64,7 +65,8 @@ def load(path: str, device="cuda") -> learned.PDNet:
     state = torch.load(path, map_location="cpu", weights_only=True)
     n_iter = int(state.pop("meta_n_iter"))
     scales = state.pop("meta_scales").tolist() if "meta_scales" in state else None
-    net = learned.PDNet(n_iter=n_iter, scales=scales)
+    init = "fdk" if int(state.pop("meta_fdk_init", torch.tensor(0))) else "zero"
+    net = learned.PDNet(n_iter=n_iter, scales=scales, init=init)
     net.perms = [list(map(int, r)) for r in state.pop("perms").tolist()]
     net.load_state_dict(state)
     return net.to(device)
@@ -86,6 +88,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n-iter", type=int, default=8)
+    ap.add_argument("--init", default="zero", choices=["zero", "fdk"])
     ap.add_argument("--scales", default=None,
                     help="comma-separated resolution divisor per iteration, e.g. 4,4,2,2,1,1")
     ap.add_argument("--pool", type=int, default=48, help="distinct training phantoms")
@@ -106,7 +109,7 @@ def main(argv=None):
     scales = [int(v) for v in args.scales.split(",")] if args.scales else None
     n_iter = len(scales) if scales else args.n_iter
     net = load(args.resume) if args.resume else \
-        learned.PDNet(n_iter, seed=args.seed, scales=scales).cuda()
+        learned.PDNet(n_iter, seed=args.seed, scales=scales, init=args.init).cuda()
     model = learned.LearnedPD(net, geo, V, L)
     opt = torch.optim.Adam(net.parameters(), lr=args.lr)
     print(f"[train] geometry {args.geometry} vol {geo.vol_shape} sino {geo.sino_shape} "

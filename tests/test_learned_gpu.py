@@ -34,14 +34,14 @@ def _say(*a):
     print(*a, flush=True)
 
 
-SCALES = [None, (2, 2, 1)]
+SCALES = [(None, "zero"), ((2, 2, 1), "zero"), ((2, 2, 1), "fdk")]
 
 
-def _setup(dev, oracle, n_iter=3, seed=0, scales=None):
+def _setup(dev, oracle, n_iter=3, seed=0, scales=None, init="zero"):
     torch, cbct, learned = dev
     g = TOY
     geo = cbct.Geometry(g)
-    net = learned.PDNet(n_iter=n_iter, seed=seed, scales=scales).cuda()
+    net = learned.PDNet(n_iter=n_iter, seed=seed, scales=scales, init=init).cuda()
     with torch.no_grad():
         for p in net.parameters():
             if p.dim() == 5:
@@ -99,16 +99,22 @@ def test_conv1_and_wresid(dev):
     assert torch.equal(g, ch[0] * (ch[1] - ch[2]))
 
 
-@pytest.mark.parametrize("scales", SCALES)
-def test_forward_matches_oracle(dev, oracle, scales):
+def _x0(oracle, g, y, L, init):
+    """The oracle's own starting reconstruction: zero or L * FDK(y)."""
+    return None if init == "zero" else L * oracle.fdk(g, y.astype(np.float64))
+
+
+@pytest.mark.parametrize("scales,init", SCALES)
+def test_forward_matches_oracle(dev, oracle, scales, init):
     torch, cbct, learned = dev
-    _say(f"[learned] forward vs oracle (toy, 3 iterations, scales {scales})")
-    g, geo, net, model, L, y, V, _ = _setup(dev, oracle, scales=scales)
+    _say(f"[learned] forward vs oracle (toy, 3 iterations, scales {scales}, init {init})")
+    g, geo, net, model, L, y, V, _ = _setup(dev, oracle, scales=scales, init=init)
+    x0 = _x0(oracle, g, y, L, init)
     xs = []
     model.reconstruct(torch.tensor(y, device="cuda"),
                       callback=lambda i, x: xs.append(x.double().cpu().numpy()))
     ref = oracle.lpd_forward(g, y.astype(np.float64), V.astype(np.float64),
-                             net.oracle_params(), L, scales=scales)
+                             net.oracle_params(), L, scales=scales, x0=x0)
     for i, (a, b) in enumerate(zip(xs, ref)):
         rel = np.linalg.norm(a - b) / np.linalg.norm(b)
         _say(f"  x_{i + 1}: rel L2 {rel:.2e}")
@@ -120,15 +126,17 @@ def test_forward_matches_oracle(dev, oracle, scales):
         for part in ("dual", "primal"):
             p[part] = [np.zeros_like(a) for a in p[part]]
     rz = oracle.lpd_forward(g, y.astype(np.float64), V.astype(np.float64), ps, L,
-                            scales=scales)[-1]
+                            scales=scales, x0=x0)[-1]
     assert np.linalg.norm(xz - rz) <= 1e-5 * np.linalg.norm(rz)
 
 
-@pytest.mark.parametrize("scales", SCALES)
-def test_gradient_matches_oracle_and_rebuilds_latents(dev, oracle, scales):
+@pytest.mark.parametrize("scales,init", SCALES)
+def test_gradient_matches_oracle_and_rebuilds_latents(dev, oracle, scales, init):
     torch, cbct, learned = dev
-    _say(f"[learned] reversible gradient vs oracle (toy, 3 iterations, scales {scales})")
-    g, geo, net, model, L, y, V, x_true = _setup(dev, oracle, seed=3, scales=scales)
+    _say(f"[learned] reversible gradient vs oracle (toy, 3 iterations, scales {scales}, "
+         f"init {init})")
+    g, geo, net, model, L, y, V, x_true = _setup(dev, oracle, seed=3, scales=scales, init=init)
+    x0 = _x0(oracle, g, y, L, init)
     fov = (V >= 0.5)
     wmask = (fov / fov.sum()).astype(np.float32)
     yt = torch.tensor(y, device="cuda")
@@ -136,7 +144,7 @@ def test_gradient_matches_oracle_and_rebuilds_latents(dev, oracle, scales):
                                torch.tensor(wmask, device="cuda"))
     rloss, rgr = oracle.lpd_loss_grad(g, y.astype(np.float64), V.astype(np.float64),
                                       net.oracle_params(), L, x_true, wmask.astype(np.float64),
-                                      scales=scales)
+                                      scales=scales, x0=x0)
     _say(f"  loss {loss:.6e} oracle {rloss:.6e}")
     assert abs(loss - rloss) <= 4e-3 * rloss
     worst = 0.0
