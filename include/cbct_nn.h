@@ -117,7 +117,9 @@ cbct_status cbct_upsample(int r, int n0, int n1, int n2, const float *in, float 
  * offset-detector redundancy weight w (1/2 for a centred panel; for an
  * offset panel sin^2(pi/4 (1 + u/Delta)) over the overlap |u| <= Delta =
  * nu du / 2 - |off_u| and 1 beyond), cosine weighting, Ram-Lak filtering
- * along panel rows, and voxel-driven backprojection with the R^2/U^2 weight
+ * along panel rows (window 0; window 1 applies the Hann window, kernel
+ * h/2 + (h(. - 1) + h(. + 1))/4 on the zero-padded row; other values:
+ * CBCT_E_ARG), and voxel-driven backprojection with the R^2/U^2 weight
  * and bilinear interpolation between pixel centres (zero off the panel).
  * sino: FP32 line integrals [n_angles][nv][nu]; work: FP32 device buffer of
  * the same size (receives the filtered projections); vol: FP32
@@ -125,8 +127,8 @@ cbct_status cbct_upsample(int r, int n0, int n1, int n2, const float *in, float 
  * (else CBCT_E_ARG); nu <= 4096 (else CBCT_E_SHAPE); an offset panel must
  * overlap the central ray (else CBCT_E_GEOM).  FP32 arithmetic.
  */
-cbct_status cbct_fdk(const cbct_geom *g, const float *sino, float *work, float *vol,
-                     void *stream);
+cbct_status cbct_fdk(const cbct_geom *g, const float *sino, int window, float *work,
+                     float *vol, void *stream);
 
 #ifdef __cplusplus
 }

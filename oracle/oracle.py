@@ -662,8 +662,17 @@ def ramp_kernel(n: np.ndarray, pitch: float) -> np.ndarray:
     return h / pitch ** 2
 
 
-def fdk_filter(g: dict, p: np.ndarray) -> np.ndarray:
-    """Steps 1-2: weighted, ramp-filtered projections q[angle][v][u]."""
+def hann_ramp_kernel(n: np.ndarray, pitch: float) -> np.ndarray:
+    """Ram-Lak kernel times the Hann window 1/2 + 1/2 cos(2 pi omega pitch)
+    in frequency: h(n)/2 + (h(n-1) + h(n+1))/4 in space."""
+    n = np.asarray(n)
+    return 0.5 * ramp_kernel(n, pitch) + 0.25 * (ramp_kernel(n - 1, pitch) +
+                                                 ramp_kernel(n + 1, pitch))
+
+
+def fdk_filter(g: dict, p: np.ndarray, window: str = "ramlak") -> np.ndarray:
+    """Steps 1-2: weighted, ramp-filtered projections q[angle][v][u]
+    (window "ramlak" or "hann")."""
     R, D = g["sid"], g["sdd"]
     u = g["off_u"] + (np.arange(g["nu"]) - 0.5 * (g["nu"] - 1)) * g["du"]
     v = g["off_v"] + (np.arange(g["nv"]) - 0.5 * (g["nv"] - 1)) * g["dv"]
@@ -671,7 +680,8 @@ def fdk_filter(g: dict, p: np.ndarray) -> np.ndarray:
     dui = g["du"] * R / D
     pre = fdk_weights(g)[None, :] * R / np.sqrt(R * R + ui[None, :] ** 2 + vi[:, None] ** 2)
     pw = np.asarray(p, np.float64) * pre[None, :, :]
-    h = ramp_kernel(np.arange(-(g["nu"] - 1), g["nu"]), dui)
+    kern = {"ramlak": ramp_kernel, "hann": hann_ramp_kernel}[window]
+    h = kern(np.arange(-(g["nu"] - 1), g["nu"]), dui)
     q = np.empty_like(pw)
     nu = g["nu"]
     for a in range(pw.shape[0]):
@@ -713,6 +723,6 @@ def fdk_backproject(g: dict, q: np.ndarray) -> np.ndarray:
     return f
 
 
-def fdk(g: dict, p: np.ndarray) -> np.ndarray:
+def fdk(g: dict, p: np.ndarray, window: str = "ramlak") -> np.ndarray:
     """FDK reconstruction [nz][ny][nx] from line integrals p[angle][v][u]."""
-    return fdk_backproject(g, fdk_filter(g, p))
+    return fdk_backproject(g, fdk_filter(g, p, window))

@@ -80,7 +80,7 @@ def _load():
     lib.cbct_pool.argtypes = [i32, i32, i32, i32, vp, vp, fl, vp]
     lib.cbct_projdown.argtypes = [i32, i32, i32, i32, vp, vp, fl, vp]
     lib.cbct_upsample.argtypes = [i32, i32, i32, i32, vp, vp, fl, i32, vp]
-    lib.cbct_fdk.argtypes = [vp, vp, vp, vp, vp]
+    lib.cbct_fdk.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.cbct_conv1.argtypes = [sz, i32, ctypes.POINTER(vp), vp, vp, i32, fl, vp]
     lib.cbct_fov_fraction.argtypes = [vp, vp]
     lib.cbct_error_string.argtypes = [i32]
@@ -532,8 +532,10 @@ def upsample(c, r, out=None, scale=1.0, accumulate=False):
 
 
 def fdk(geom: Geometry, sino: torch.Tensor, out: torch.Tensor | None = None,
-        work: torch.Tensor | None = None) -> torch.Tensor:
-    """FDK reconstruction with offset-detector redundancy weights (FP32)."""
+        work: torch.Tensor | None = None, window: str = "ramlak") -> torch.Tensor:
+    """FDK reconstruction with offset-detector redundancy weights (FP32);
+    window "ramlak" or "hann"."""
+    win = {"ramlak": 0, "hann": 1}[window]
     if tuple(sino.shape) != tuple(geom.sino_shape):
         raise ValueError("sinogram shape does not match the geometry")
     if out is None:
@@ -541,6 +543,6 @@ def fdk(geom: Geometry, sino: torch.Tensor, out: torch.Tensor | None = None,
     if work is None:
         work = torch.empty(geom.sino_shape, dtype=torch.float32, device=sino.device)
     with torch.cuda.device(geom.device):
-        _check(_lib.cbct_fdk(geom.handle, _f32(sino, "sino"), _f32(work, "work"),
+        _check(_lib.cbct_fdk(geom.handle, _f32(sino, "sino"), win, _f32(work, "work"),
                              _f32(out, "out"), _stream(geom.device)), "cbct_fdk")
     return out

@@ -101,6 +101,7 @@ def main(argv=None):
         # FDK (offset-detector weights) on the same data: A x = L y
         t_fdk = timed(lambda mark: (cbct.fdk(geo, y_cg), mark(1)), 1)[0]
         ps_fdk = psnr(cbct.fdk(geo, y_cg), xt, peak)
+        ps_fdk_h = psnr(cbct.fdk(geo, y_cg, window="hann"), xt, peak)
         n = net.n_iter
         t_ln = timed(lambda mark: model.reconstruct(y, callback=lambda i, x: mark(i)), n)
         ps_ln = []
@@ -123,10 +124,11 @@ def main(argv=None):
              "learned_psnr_db": [round(v, 3) for v in ps_ln],
              "learned_time_s": [round(v, 4) for v in t_ln],
              "zero_block_psnr_db": [round(v, 3) for v in ps_zero],
-             "fdk_psnr_db": round(ps_fdk, 3), "fdk_time_s": round(t_fdk, 4),
+             "fdk_psnr_db": round(ps_fdk, 3), "fdk_hann_psnr_db": round(ps_fdk_h, 3),
+             "fdk_time_s": round(t_fdk, 4),
              "cgls_time_to_target_s": first(ps_cg, t_cg),
              "learned_time_to_target_s": first(ps_ln, t_ln)}
-        print(f"[compare]   FDK {ps_fdk:.2f} dB ({t_fdk:.3f} s)", flush=True)
+        print(f"[compare]   FDK {ps_fdk:.2f} dB, Hann {ps_fdk_h:.2f} dB ({t_fdk:.3f} s)", flush=True)
         print(f"[compare]   learned {ps_ln[-1]:.2f} dB after {n} iterations ({t_ln[-1]:.3f} s); "
               f"zero-block net {ps_zero[-1]:.2f} dB; time to {target:.2f} dB: CGLS "
               f"{r['cgls_time_to_target_s']} s, learned {r['learned_time_to_target_s']} s",
@@ -140,6 +142,8 @@ def main(argv=None):
         "zero_block_psnr_db_mean": round(float(np.mean([r["zero_block_psnr_db"][-1]
                                                           for r in results])), 3),
         "fdk_psnr_db_mean": round(float(np.mean([r["fdk_psnr_db"] for r in results])), 3),
+        "fdk_hann_psnr_db_mean": round(float(np.mean([r["fdk_hann_psnr_db"] for r in results])),
+                                       3),
         "net": {"iterations": net.n_iter, "scales": list(net.scales), "init": net.init},
         "results": results,
     }

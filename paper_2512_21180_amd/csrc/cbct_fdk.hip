@@ -13,9 +13,13 @@
 // (s = sign(off_u)) and 1 beyond it, so conjugate rays' weights add to one
 // (Wang, Med. Phys. 2002).
 //
+// Optional Hann apodisation of the ramp (gain |omega| (1/2 + 1/2 cos(2 pi
+// omega du_i)), the spatial kernel h/2 + (h(. - 1) + h(. + 1))/4).
+//
 // Filter: one workgroup per panel row of one projection; the weighted row
-// is staged in LDS between two zero pads of nu words, so every output sums
-// all odd offsets in one fixed order without bounds tests.  Backprojection:
+// is staged in LDS between two zero pads of nu + 1 words, so every output
+// sums all odd offsets in one fixed order without bounds tests; the ramp
+// output is formed at columns -1 .. nu and the Hann window applied to it.  Backprojection:
 // one thread per voxel, angles in order, the sum in a register.
 #include <hip/hip_runtime.h>
 
@@ -34,6 +38,7 @@ struct FdkArgs {
     DevGeom g;
     float R, D, dui, delta, sgn;   // sgn = 0: centred panel (w = 1/2)
     float dbeta;
+    int hann;                      // 1: Hann-apodised ramp
 };
 
 __device__ inline float red_weight(const FdkArgs &A, float u)
@@ -52,8 +57,10 @@ __global__ void __launch_bounds__(kT) k_fdk_filter(FdkArgs A, const float *p, fl
     extern __shared__ float lds[];
     const DevGeom &g = A.g;
     const int nu = g.nu;
-    float *row = lds + nu;             // lds[0, nu) and lds[2 nu, 3 nu) stay zero
-    float *coef = lds + 3 * nu;        // coef[m] = 1 / (pi^2 (2m+1)^2)
+    const int P = nu + 1;              // zero pads of nu + 1 words on each side
+    float *row = lds + P;
+    float *coef = lds + 2 * P + nu;    // coef[m] = 1 / (pi^2 (2m+1)^2)
+    float *qr = coef + (nu + 1) / 2;   // ramp output at columns -1 .. nu
     const int a = blockIdx.x / g.nv, iv = blockIdx.x % g.nv;
     const size_t base = ((size_t)a * g.nv + iv) * nu;
     const float vi = (g.off_v + ((float)iv - g.cv) * g.dv) * (A.R / A.D);
@@ -62,8 +69,10 @@ __global__ void __launch_bounds__(kT) k_fdk_filter(FdkArgs A, const float *p, fl
         const float ui = u * (A.R / A.D);
         const float cw = A.R * rsqrtf(fmaf(A.R, A.R, fmaf(ui, ui, vi * vi)));
         row[k] = p[base + k] * red_weight(A, u) * cw;
+    }
+    for (int k = threadIdx.x; k < P; k += kT) {
         lds[k] = 0.0f;
-        lds[2 * nu + k] = 0.0f;
+        lds[P + nu + k] = 0.0f;
     }
     for (int m = threadIdx.x; m < (nu + 1) / 2; m += kT) {
         const float n = (float)(2 * m + 1);
@@ -71,14 +80,19 @@ __global__ void __launch_bounds__(kT) k_fdk_filter(FdkArgs A, const float *p, fl
     }
     __syncthreads();
     const float scale = 1.0f / A.dui;  // du_i * h, h ~ 1 / du_i^2
-    for (int j = threadIdx.x; j < nu; j += kT) {
+    // Ram-Lak output at columns -1 .. nu (the zero-padded row's convolution)
+    for (int j = threadIdx.x - 1; j <= nu; j += kT) {
         float acc = 0.0f;
         for (int m = 0; m < (nu + 1) / 2; ++m) {
             const int n = 2 * m + 1;
             acc = fmaf(coef[m], row[j - n] + row[j + n], acc);
         }
-        q[base + j] = scale * fmaf(0.25f, row[j], -acc);
+        qr[j + 1] = scale * fmaf(0.25f, row[j], -acc);
     }
+    __syncthreads();
+    // Hann window: the kernel h/2 + (h(. - 1) + h(. + 1))/4
+    for (int j = threadIdx.x; j < nu; j += kT)
+        q[base + j] = A.hann ? fmaf(0.5f, qr[j + 1], 0.25f * (qr[j] + qr[j + 2])) : qr[j + 1];
 }
 
 __global__ void __launch_bounds__(kT) k_fdk_backproject(FdkArgs A, const float *q, float *f)
@@ -127,11 +141,13 @@ __global__ void __launch_bounds__(kT) k_fdk_backproject(FdkArgs A, const float *
 
 using namespace cbct;
 
-extern "C" cbct_status cbct_fdk(const cbct_geom *g, const float *sino, float *work, float *vol,
-                                void *stream)
+extern "C" cbct_status cbct_fdk(const cbct_geom *g, const float *sino, int window, float *work,
+                                float *vol, void *stream)
 {
     if (!g || !sino || !work || !vol)
         return CBCT_E_NULL;
+    if (window != 0 && window != 1)
+        return CBCT_E_ARG;
     if (!g->dev_block)
         return CBCT_E_ARG;
     const cbct_geom_desc &d = g->desc;
@@ -154,8 +170,9 @@ extern "C" cbct_status cbct_fdk(const cbct_geom *g, const float *sino, float *wo
     if (A.sgn != 0.0f && !(A.delta > 0))
         return CBCT_E_GEOM;   // no overlap: no redundancy weighting possible
     A.dbeta = (float)(2.0 * M_PI / n);
+    A.hann = window;
     hipStream_t s = (hipStream_t)stream;
-    const size_t lds = (3 * (size_t)d.nu + (d.nu + 1) / 2) * sizeof(float);
+    const size_t lds = (2 * ((size_t)d.nu + 1) + d.nu + (d.nu + 1) / 2 + d.nu + 2) * sizeof(float);
     hipLaunchKernelGGL(k_fdk_filter, dim3((unsigned)((size_t)n * d.nv)), dim3(kT), lds, s, A,
                        sino, work);
     const size_t nvox = (size_t)d.nx * d.ny * d.nz;

@@ -254,8 +254,8 @@ class LearnedPD:
 
     def init_state(self, y: torch.Tensor, ys=None):
         """Latents at the first iteration's resolution and x_0 (zero, or the
-        FDK reconstruction of Alg. 1: since A x = L y for normalised data,
-        x_0 = L FDK(y))."""
+        FDK reconstruction of Alg. 1 with the Hann-apodised ramp: since
+        A x = L y for normalised data, x_0 = L FDK(y))."""
         geo, L = self.geo, self.L
         r0 = self.net.scales[0]
         ys = self._data(y) if ys is None else ys
@@ -264,7 +264,7 @@ class LearnedPD:
         if r0 != 1:
             xbp = cbct.pool(xbp, r0)
         if self.net.init == "fdk":
-            x = cbct.fdk(geo, y)
+            x = cbct.fdk(geo, y, window="hann")
             cbct.axpby(x, L, x, 0.0, x)
             xb = x if r0 == 1 else cbct.pool(x, r0)
         else:

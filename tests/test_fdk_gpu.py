@@ -27,16 +27,17 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("window", ["ramlak", "hann"])
 @pytest.mark.parametrize("k", range(len(CASES)))
-def test_fdk_matches_oracle(dev, oracle, k):
+def test_fdk_matches_oracle(dev, oracle, k, window):
     torch, cbct = dev
     g = CASES[k]
-    print(f"[fdk] case {k}", flush=True)
+    print(f"[fdk] case {k} window {window}", flush=True)
     x = W.phantom_c1(g, 70 + k)[0]
     p = oracle.forward(g, x) + 1e-3 * W.rng(80 + k).standard_normal(W.sino_shape(g))
-    ref = oracle.fdk(g, p)
+    ref = oracle.fdk(g, p, window)
     geo = cbct.Geometry(g)
-    got = cbct.fdk(geo, torch.tensor(p, dtype=torch.float32, device="cuda"))
+    got = cbct.fdk(geo, torch.tensor(p, dtype=torch.float32, device="cuda"), window=window)
     got = got.double().cpu().numpy()
     rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"  rel L2 {rel:.2e}", flush=True)

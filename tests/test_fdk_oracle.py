@@ -5,7 +5,8 @@ offset-detector redundancy weights):
   w = 1 where only one is, w = 1/2 for a centred panel;
 * Ram-Lak kernel: its discrete-time Fourier transform is exactly |omega|
   (cycles per mm) below Nyquist, so a filtered cosine row is |omega| times
-  the cosine away from the row ends;
+  the cosine away from the row ends; with the Hann window the gain is
+  |omega| (1/2 + 1/2 cos(2 pi omega pitch));
 * reconstruction: uniform balls, centred and far off-centre, are recovered
   to 1 % mean error and 0.5 % mean bias inside (centred panel); with the
   offset panel, to 1 % at the centre and 2.5 % off-centre (the known bias of
@@ -43,6 +44,11 @@ def test_ramp_filter_response(oracle):
         q = np.convolve(row, h)[N - 1:2 * N - 1] * pitch
         mid = slice(N // 2 - 200, N // 2 + 200)
         assert np.allclose(q[mid], omega * row[mid], atol=2e-3 * max(omega, 0.05)), omega
+        # Hann apodisation: |omega| (1/2 + 1/2 cos(2 pi omega pitch))
+        hh = oracle.hann_ramp_kernel(n, pitch)
+        qh = np.convolve(row, hh)[N - 1:2 * N - 1] * pitch
+        gain = omega * (0.5 + 0.5 * np.cos(2 * np.pi * omega * pitch))
+        assert np.allclose(qh[mid], gain * row[mid], atol=2e-3 * max(omega, 0.05)), omega
 
 
 def _ball(g, centre, radius, mu=0.02):

@@ -101,7 +101,7 @@ def test_conv1_and_wresid(dev):
 
 def _x0(oracle, g, y, L, init):
     """The oracle's own starting reconstruction: zero or L * FDK(y)."""
-    return None if init == "zero" else L * oracle.fdk(g, y.astype(np.float64))
+    return None if init == "zero" else L * oracle.fdk(g, y.astype(np.float64), "hann")
 
 
 @pytest.mark.parametrize("scales,init", SCALES)
