@@ -99,7 +99,8 @@ typedef struct cbct_geom cbct_geom;   /* opaque, immutable after creation */
  * min(sid, sdd - sid) about z (so some sample would not lie strictly between
  * source and panel), a ray is steeper in z than in x and y
  * (|d_z| >= max(|d_x|, |d_y|)), the columns of one angle change sampling axis
- * more than once, or a size exceeds 2^31 elements.  On success *out
+ * more than once, a size exceeds 2^31 elements, or one of nu, nv, nx, ny, nz
+ * exceeds 65536.  On success *out
  * receives a handle to release with cbct_geom_destroy.
  */
 cbct_status cbct_geom_create(const cbct_geom_desc *desc, cbct_geom **out);

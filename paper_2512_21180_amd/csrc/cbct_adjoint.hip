@@ -230,7 +230,9 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
             const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
             if (w == 0)
                 cr[uu] = make_float4(col.pb, col.ps, col.t0, col.tau);
-            const typename SS::T *ycol = y + (size_t)a * g.nv * g.nu + U0 + uu;
+            // 32-bit offsets within this projection (nv nu < 2^24 words)
+            const typename SS::T *ya = y + (size_t)a * g.nv * g.nu;
+            const int u = U0 + uu;
             float *dst = yt + uu * HS;
             for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
                 float val[kSB], vsq[kSB];
@@ -238,14 +240,14 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
                 for (int j = 0; j < kSB; ++j) {
                     const int v = V0 + vv0 + 4 * j;
                     const bool live = v <= V1;   // rows V1+1 .. V0+Hs-1 are zero
-                    val[j] = live ? SS::ld(ycol, (size_t)v * g.nu) : 0.0f;
+                    val[j] = live ? SS::ld(ya, (size_t)(__mul24(v, g.nu) + u)) : 0.0f;
                     vsq[j] = live ? g.rows[v].y : 0.0f;
                 }
 #pragma unroll
                 for (int j = 0; j < kSB; ++j) {
                     const int vv = vv0 + 4 * j;
                     if (vv < Hs)
-                        dst[vv] = val[j] * (col.dsf * sqrtf(col.n2 + vsq[j]));
+                        dst[vv] = val[j] * ray_ds(col.dsf, col.n2, vsq[j]);
                 }
             }
         }

@@ -156,7 +156,7 @@ __device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R,
             const int vr = w * R + r;
             if (r < R && vr < T.nv_t) {
                 const int iv = T.v0 + vr;
-                const float ds = ds0 * sqrtf(c.n2 + g.rows[iv].y);
+                const float ds = ray_ds(ds0, c.n2, g.rows[iv].y);
                 SS::st(sino, ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + lane, acc[r] * ds);
             }
         }

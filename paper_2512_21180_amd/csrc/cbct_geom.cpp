@@ -98,6 +98,9 @@ static cbct_status validate(const cbct_geom_desc &d, const std::vector<double> &
     if ((int64_t)d.n_angles * d.nv * d.nu >= (int64_t(1) << 31) ||
         (int64_t)d.nx * d.ny * d.nz >= (int64_t(1) << 31))
         return CBCT_E_GEOM;
+    // kernels index one projection with 24-bit multiplies
+    if (d.nu > 65536 || d.nv > 65536 || d.nx > 65536 || d.ny > 65536 || d.nz > 65536)
+        return CBCT_E_GEOM;
     for (double a : ang)
         if (!std::isfinite(a))
             return CBCT_E_GEOM;

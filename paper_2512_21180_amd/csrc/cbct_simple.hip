@@ -75,7 +75,7 @@ forward_simple(DevGeom g, const typename VS::T *__restrict__ vol, typename SS::T
         const float hi = fmaf(wq, v11 - v01, v01);
         acc += fmaf(wk, hi - lo, lo);
     }
-    const float ds = c.dsf * sqrtf(c.n2 + row.y);
+    const float ds = ray_ds(c.dsf, c.n2, row.y);
     SS::st(sino, ch * nsino + ((size_t)a * g.nv + iv) * g.nu + iu, acc * ds);
 }
 
@@ -119,7 +119,7 @@ __device__ inline float gather_columns(const DevGeom &g, int a, int u_lo, int u_
             const float wk = 1.0f - fabsf(kk - (float)k);
             if (!(wk > 0.0f))
                 continue;
-            const float ds = c.dsf * sqrtf(c.n2 + row.y);
+            const float ds = ray_ds(c.dsf, c.n2, row.y);
             col = fmaf(ds * wk, SS::ld(y, ((size_t)a * g.nv + v) * g.nu + u), col);
         }
         acc = fmaf(wq, col, acc);

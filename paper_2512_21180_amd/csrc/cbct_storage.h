@@ -54,4 +54,13 @@ inline hipError_t dispatch_storage(cbct_dtype vt, cbct_dtype st, F &&f)
     return hipErrorInvalidValue;
 }
 
+// Ray length per plane, ds = dsf * sqrt(n2 + V^2), for a column with
+// constants (dsf, n2) and a row with V^2 = v2.  Every kernel computes ds with
+// this one function (the hardware square root, within 1 ulp), so the forward
+// and the adjoint apply the same weights.
+__device__ inline float ray_ds(float dsf, float n2, float v2)
+{
+    return dsf * __builtin_amdgcn_sqrtf(n2 + v2);
+}
+
 }  // namespace cbct
