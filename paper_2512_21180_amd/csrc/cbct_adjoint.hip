@@ -15,9 +15,11 @@
 // pre-multiplied by the ray length per plane ds, together with the column
 // constants.  Per voxel and column, the rows with non-zero weight form a run
 // that starts below the row where the ray crosses z = k - 1 and holds at
-// most NT rows; the taps use the clamped hat, so rows past the run add zero.
+// most NT rows; the taps use the clamped hat, so rows outside the run add
+// exact zeros (a run that would leave the window starts lower instead).
 // The window is stored column-major, so a run is consecutive LDS words read
 // two at a time with immediate offsets in a fully unrolled sequence.
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,8 +31,12 @@ namespace cbct {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBI = 8, kBJ = 8, kBK = 16, kV = 4;
-constexpr int kSB = 8;   // rows per staging batch (loads in flight per thread)
+constexpr int kBI = 8, kBJ = 8;
+// Bricks are 8 x 8 x 16: four voxels per thread along z, one channel per
+// window element (the gather is written for C channels per element and KV
+// voxels per thread; a four-channel 8 x 8 x 4 variant measured 1.6x slower
+// per channel than this one and was dropped).
+constexpr int kKV1 = 4;
 
 struct BrickArgs {
     DevGeom g;
@@ -60,18 +66,20 @@ struct GatherIn {
     const float *yt;
     const float4 *cr;
     int HS, U0, U1, V0, V1;
+    int VS1;   // largest run start: max(V1 - NT + 1, V0), so a run ends in the window
     int ic, jc, k0;
     float cxv, cyv, inv_du, inv_rvs;
 };
 
-// Accumulate one angle's contributions into acc, reading 2 NP taps per voxel
-// and column (rows past the non-zero run have zero weight).
-template <int NP>
-__device__ inline void gather_angle(const GatherIn &in, float (&acc)[kV])
+// Accumulate one angle's contributions into acc, reading NT taps per voxel
+// and column (rows past the non-zero run have zero weight).  The window holds
+// C channels per element; KV voxels per thread along z.
+template <int NT, int C, int KV>
+__device__ inline void gather_angle(const GatherIn &in, float (&acc)[KV][C])
 {
     const DevGeom &g = in.g;
     const AngRec &ar = in.ar;
-    const int HS = in.HS, U0 = in.U0, U1 = in.U1, V0 = in.V0, V1 = in.V1;
+    const int HS = in.HS, U0 = in.U0, U1 = in.U1, V0 = in.V0, VS1 = in.VS1;
     const int ic = in.ic, jc = in.jc, k0 = in.k0;
     const float cxv = in.cxv, cyv = in.cyv, inv_du = in.inv_du, inv_rvs = in.inv_rvs;
     const float *yt = in.yt;
@@ -106,69 +114,82 @@ for (int cls = 0; cls < 2; ++cls) {
         // weight: drop them when their own weight (computed as in the loop)
         // is zero, so no non-zero term is ever skipped.
         if (ul <= uh) {
-            const float4 C = cr[ul - U0];
-            if (fabsf(fmaf(fp, C.y, C.x) - qv) >= 1.0f)
+            const float4 cq = cr[ul - U0];
+            if (fabsf(fmaf(fp, cq.y, cq.x) - qv) >= 1.0f)
                 ++ul;
         }
         if (ul <= uh) {
-            const float4 C = cr[uh - U0];
-            if (fabsf(fmaf(fp, C.y, C.x) - qv) >= 1.0f)
+            const float4 cq = cr[uh - U0];
+            if (fabsf(fmaf(fp, cq.y, cq.x) - qv) >= 1.0f)
                 --uh;
         }
         for (int u = ul; u <= uh; ++u) {
             if (cls == 1 && u >= ar.x_lo && u < ar.x_hi)
                 continue;   // those columns are sampled on x planes
-            const float4 C = cr[u - U0];
-            const float q = fmaf(fp, C.y, C.x);
+            const float4 cq = cr[u - U0];
+            const float q = fmaf(fp, cq.y, cq.x);
             const float wq = sat(1.0f - fabsf(q - qv));
-            const float t = fmaf(fp, C.w, C.z);
+            const float t = fmaf(fp, cq.w, cq.z);
             const float beta = t * g.rvs;
             const float rt = __builtin_amdgcn_rcpf(t);
             // row where the ray crosses z index kk - 1: vA + kk vB
             const float vB = rt * inv_rvs;
             const float vA = fmaf(fmaf(-1.0f - g.Kb, rt, -g.rv0), inv_rvs, g.cv);
-            const float *ycol = yt + (u - U0) * HS - V0;
+            const float *ycol = yt + ((u - U0) * HS - V0) * C;
 #pragma unroll
-            for (int n = 0; n < kV; ++n) {
+            for (int n = 0; n < KV; ++n) {
                 const float kk = (float)(k0 + n);
-                // one row below that crossing, for rounding
-                const int vs = min(max((int)floorf(fmaf(kk, vB, vA)) - 1, V0), V1);
+                // one row below that crossing, for rounding; a start moved
+                // down to VS1 only adds rows below the run (zero weight)
+                const int vs = min(max((int)floorf(fmaf(kk, vB, vA)) - 1, V0), VS1);
                 float s = fmaf(t, fmaf((float)vs - g.cv, g.rvs, g.rv0), g.Kb - kk);
-                const float *py = ycol + vs;
-                float csum = 0.0f;
-                float yv[2 * NP];
+                const float *py = ycol + vs * C;
+                float csum[C];
 #pragma unroll
-                for (int m = 0; m < 2 * NP; ++m)
+                for (int ch = 0; ch < C; ++ch)
+                    csum[ch] = 0.0f;
+                float yv[NT * C];
+#pragma unroll
+                for (int m = 0; m < NT * C; ++m)
                     yv[m] = py[m];
 #pragma unroll
-                for (int m = 0; m < 2 * NP; ++m) {
-                    csum = fmaf(sat(1.0f - fabsf(s)), yv[m], csum);
+                for (int m = 0; m < NT; ++m) {
+                    const float wz = sat(1.0f - fabsf(s));
+#pragma unroll
+                    for (int ch = 0; ch < C; ++ch)
+                        csum[ch] = fmaf(wz, yv[m * C + ch], csum[ch]);
                     s += beta;
                 }
-                acc[n] = fmaf(wq, csum, acc[n]);
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    acc[n][ch] = fmaf(wq, csum[ch], acc[n][ch]);
             }
         }
     }
 }
 
-// Gather one brick (index b) of one channel: y is that channel's sinogram,
-// vol that channel's volume.  `lds` holds the panel window, column-major
-// ([W][HS], HS odd so that a row of lanes writes distinct banks), and the
-// column table.
-template <class SS, class VS>
-__device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__restrict__ y,
-                             typename VS::T *__restrict__ vol, float *lds)
+// Gather one brick (index b) for C channels (the first nch of them live):
+// ys[c] is channel c's sinogram, vols[c] its volume.  Bricks are 8 x 8 x 4 KV
+// voxels; thread (lane, wave w) owns voxel column (lane % 8, lane / 8) and
+// the KV voxels from 4 KV (brick z) + KV w up.  `lds` holds the panel window,
+// column-major with C channels per element ([W][HS][C], HS odd so that a row
+// of lanes writes distinct banks), and the column table.
+template <class SS, class VS, int C, int KV>
+__device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *const (&ys)[C],
+                             typename VS::T *const (&vols)[C], int nch, float *lds)
 {
+    constexpr int kBK = 4 * KV;
+    constexpr int kSB = C == 1 ? 8 : 4;   // rows per staging batch (loads in flight)
     const DevGeom &g = A.g;
     const int HS = A.HS;
-    float *yt = lds;                                    // [W][HS] ds-weighted panel window
-    float4 *cr = (float4 *)(lds + (size_t)A.W * HS);    // [W] (pb, ps, t0, tau)
+    float *yt = lds;                                        // ds-weighted panel window
+    float4 *cr = (float4 *)(lds + (size_t)A.W * HS * C);    // [W] (pb, ps, t0, tau)
 
     const int bx = b % A.nbx, by = (b / A.nbx) % A.nby, bz = b / (A.nbx * A.nby);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int i = bx * kBI + (lane & 7), j = by * kBJ + (lane >> 3);
-    const int k0 = bz * kBK + w * kV;
+    const int k0 = bz * kBK + w * KV;
     const int ic = min(i, g.nx - 1), jc = min(j, g.ny - 1);
     const float cxv = g.ox + ((float)ic - 0.5f * (float)(g.nx - 1)) * g.vx;
     const float cyv = g.oy + ((float)jc - 0.5f * (float)(g.ny - 1)) * g.vy;
@@ -188,7 +209,12 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
     // z of this wave's first voxel layer (wave-uniform)
     const float zc_w0 = g.oz + ((float)k0 - 0.5f * (float)(g.nz - 1)) * g.vz;
     const float inv_rvs = 1.0f / g.rvs;
-    float acc[kV] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float acc[KV][C];
+#pragma unroll
+    for (int n = 0; n < KV; ++n)
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            acc[n][ch] = 0.0f;
 
     __syncthreads();   // the previous work item's readers of lds are done
     for (int a = 0; a < g.n_angles; ++a) {
@@ -216,11 +242,14 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
         int NT = adj_taps_rounded(min((int)floorf(2.0f / (tmin * g.rvs)) + 3, A.NTmax));
         NT = __builtin_amdgcn_readfirstlane(NT);
         const int V0 = max((int)floorf(vmin) - 2, 0);
-        const int V1 = min(min((int)ceilf(vmax) + 2, g.nv - 1), V0 + A.H - NT - 1);
+        const int V1 = min(min((int)ceilf(vmax) + 2, g.nv - 1), V0 + A.H - 1);
         if (U0 > U1 || V0 > V1)
             continue;
         const int Wc = U1 - U0 + 1;
-        const int Hs = V1 - V0 + 1 + NT;   // staged rows (rows past V1 are zero)
+        // staged rows; rows past V1 (only when the window is shorter than a
+        // run) are zero
+        const int Hs = max(V1 - V0 + 1, NT);
+        const int VS1 = max(V1 - NT + 1, V0);
 
         __syncthreads();   // previous angle's readers are done
         // Columns on lanes, rows on waves (stride 4).  The loads of kSB rows
@@ -231,35 +260,48 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
             if (w == 0)
                 cr[uu] = make_float4(col.pb, col.ps, col.t0, col.tau);
             // 32-bit offsets within this projection (nv nu < 2^24 words)
-            const typename SS::T *ya = y + (size_t)a * g.nv * g.nu;
+            const size_t pa = (size_t)a * g.nv * g.nu;
             const int u = U0 + uu;
-            float *dst = yt + uu * HS;
+            float *dst = yt + (size_t)uu * HS * C;
             for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
-                float val[kSB], vsq[kSB];
+                float val[kSB][C], vsq[kSB];
 #pragma unroll
-                for (int j = 0; j < kSB; ++j) {
-                    const int v = V0 + vv0 + 4 * j;
+                for (int jj = 0; jj < kSB; ++jj) {
+                    const int v = V0 + vv0 + 4 * jj;
                     const bool live = v <= V1;   // rows V1+1 .. V0+Hs-1 are zero
-                    val[j] = live ? SS::ld(ya, (size_t)(__mul24(v, g.nu) + u)) : 0.0f;
-                    vsq[j] = live ? g.rows[v].y : 0.0f;
+                    const size_t off = pa + (size_t)(__mul24(v, g.nu) + u);
+#pragma unroll
+                    for (int ch = 0; ch < C; ++ch)
+                        val[jj][ch] = (live && (C == 1 || ch < nch)) ? SS::ld(ys[ch], off) : 0.0f;
+                    vsq[jj] = live ? g.rows[v].y : 0.0f;
                 }
 #pragma unroll
-                for (int j = 0; j < kSB; ++j) {
-                    const int vv = vv0 + 4 * j;
-                    if (vv < Hs)
-                        dst[vv] = val[j] * ray_ds(col.dsf, col.n2, vsq[j]);
+                for (int jj = 0; jj < kSB; ++jj) {
+                    const int vv = vv0 + 4 * jj;
+                    if (vv < Hs) {
+                        const float ds = ray_ds(col.dsf, col.n2, vsq[jj]);
+                        if constexpr (C == 4) {
+                            *reinterpret_cast<float4 *>(dst + (size_t)vv * 4) =
+                                make_float4(val[jj][0] * ds, val[jj][1] * ds, val[jj][2] * ds,
+                                            val[jj][3] * ds);
+                        } else {
+#pragma unroll
+                            for (int ch = 0; ch < C; ++ch)
+                                dst[(size_t)vv * C + ch] = val[jj][ch] * ds;
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
 
-        // ---- this wave's four voxel layers (z of the voxel centres +- one
+        // ---- this wave's KV voxel layers (z of the voxel centres +- one
         // pitch) land on rows [wv0, wv1] for every ray through the brick's
         // box (lambda is extreme at the box corners); a wave whose rows miss
         // the staged rows entirely has only zero weights and skips the angle
         // (wave-uniform branch; one row of margin for rounding).
         {
-            const float zl = zc_w0 - g.vz, zh = zc_w0 + (float)(kV - 1) * g.vz + g.vz;
+            const float zl = zc_w0 - g.vz, zh = zc_w0 + (float)(KV - 1) * g.vz + g.vz;
             const float wv0 = fmaf(fminf(lmin * zl, lmax * zl) - g.off_v, inv_dv, g.cv);
             const float wv1 = fmaf(fmaxf(lmin * zh, lmax * zh) - g.off_v, inv_dv, g.cv);
             if (wv1 < (float)V0 - 1.0f || wv0 > (float)V1 + 1.0f)
@@ -267,28 +309,32 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *__
         }
         // ---- gather with a compile-time tap count (NT rounded up to a
         // supported even count; extra taps read zero weight)
-        const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, V1, ic, jc, k0, cxv, cyv, inv_du,
+        const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, V1, VS1, ic, jc, k0, cxv, cyv, inv_du,
                           inv_rvs};
         switch (NT) {
-        case 4: gather_angle<2>(in, acc); break;
-        case 6: gather_angle<3>(in, acc); break;
-        case 8: gather_angle<4>(in, acc); break;
-        case 10: gather_angle<5>(in, acc); break;
-        case 12: gather_angle<6>(in, acc); break;
-        case 14: gather_angle<7>(in, acc); break;
-        case 16: gather_angle<8>(in, acc); break;
-        case 20: gather_angle<10>(in, acc); break;
-        case 24: gather_angle<12>(in, acc); break;
-        default: gather_angle<16>(in, acc); break;
+        case 4: gather_angle<4, C, KV>(in, acc); break;
+        case 6: gather_angle<6, C, KV>(in, acc); break;
+        case 8: gather_angle<8, C, KV>(in, acc); break;
+        case 10: gather_angle<10, C, KV>(in, acc); break;
+        case 12: gather_angle<12, C, KV>(in, acc); break;
+        case 14: gather_angle<14, C, KV>(in, acc); break;
+        case 16: gather_angle<16, C, KV>(in, acc); break;
+        case 20: gather_angle<20, C, KV>(in, acc); break;
+        case 24: gather_angle<24, C, KV>(in, acc); break;
+        default: gather_angle<32, C, KV>(in, acc); break;
         }
     }
 
     if (i < g.nx && j < g.ny) {
 #pragma unroll
-        for (int n = 0; n < kV; ++n) {
+        for (int n = 0; n < KV; ++n) {
             const int k = k0 + n;
-            if (k < g.nz)
-                VS::st(vol, ((size_t)k * g.ny + j) * g.nx + i, acc[n]);
+            if (k < g.nz) {
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    if (C == 1 || ch < nch)
+                        VS::st(vols[ch], ((size_t)k * g.ny + j) * g.nx + i, acc[n][ch]);
+            }
         }
     }
 }
@@ -308,7 +354,9 @@ adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
-    gather_brick<SS, VS>(A, b, sino + ch * nsino, vol + ch * nvox, lds);
+    const typename SS::T *ys[1] = {sino + ch * nsino};
+    typename VS::T *vs[1] = {vol + ch * nvox};
+    gather_brick<SS, VS, 1, kKV1>(A, b, ys, vs, 1, lds);
 }
 
 // ---- batched adjoint: one launch over all (case, brick) items ---------------
@@ -337,33 +385,34 @@ adjoint_batch(BatchAdjArgs B)
     while (cs + 1 < B.n_cases && item >= B.first[cs + 1])
         ++cs;
     const AdjCase &C = B.c[cs];
-    gather_brick<SS, VS>(C.A, item - B.first[cs], (const typename SS::T *)C.sino,
-                         (typename VS::T *)C.vol, lds);
+    const typename SS::T *ys[1] = {(const typename SS::T *)C.sino};
+    typename VS::T *vs[1] = {(typename VS::T *)C.vol};
+    gather_brick<SS, VS, 1, kKV1>(C.A, item - B.first[cs], ys, vs, 1, lds);
 }
 
 }  // namespace
 
-static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
+static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p, int bk)
 {
     return BrickArgs{g, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI, (g.ny + kBJ - 1) / kBJ,
-                     (g.nz + kBK - 1) / kBK};   // WS: column stride of the window
+                     (g.nz + bk - 1) / bk};   // WS: column stride of the window
 }
 
-static size_t brick_lds(const AdjPlan &p)
+static size_t brick_lds(const AdjPlan &p, int channels)
 {
-    return ((size_t)p.W * p.WS + (size_t)p.W * 4) * sizeof(float);
+    return ((size_t)p.W * p.WS * channels + (size_t)p.W * 4) * sizeof(float);
 }
 
 hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *sino,
                                 cbct_dtype st, void *vol, cbct_dtype vt, int channels,
                                 hipStream_t s)
 {
-    BrickArgs A = brick_args(g, p);
+    BrickArgs A = brick_args(g, p, 4 * kKV1);
     dim3 grid(A.nbx * A.nby * A.nbz, channels), block(kThreads);
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
-        hipLaunchKernelGGL((adjoint_brick<SS, VS>), grid, block, brick_lds(p), s, A,
+        hipLaunchKernelGGL((adjoint_brick<SS, VS>), grid, block, brick_lds(p, 1), s, A,
                            (const typename SS::T *)sino, (typename VS::T *)vol);
         return hipGetLastError();
     });
@@ -379,9 +428,9 @@ hipError_t launch_adjoint_batch(int n, const cbct_geom *const *gs, const void *c
     for (int i = 0; i < n; ++i) {
         const cbct_geom *g = gs[i];
         B.first[i] = items;
-        B.c[i] = AdjCase{brick_args(g->dev, g->adj), sinos[i], vols[i]};
+        B.c[i] = AdjCase{brick_args(g->dev, g->adj, 4 * kKV1), sinos[i], vols[i]};
         items += B.c[i].A.nbx * B.c[i].A.nby * B.c[i].A.nbz;
-        lds = std::max(lds, brick_lds(g->adj));
+        lds = std::max(lds, brick_lds(g->adj, 1));
     }
     B.first[n] = items;
     B.n_items = items;

@@ -82,7 +82,7 @@ __host__ __device__ inline int adj_taps_rounded(int nt)
 }
 
 // Adjoint plan: bricks of 8 x 8 x 16 voxels; per angle the brick's panel
-// footprint (at most W x H pixels, taps included) is staged in LDS.
+// footprint (at most W x H pixels, clipped to the panel) is staged in LDS.
 struct AdjPlan {
     bool ok = false;   // false: fall back to the one-thread-per-voxel kernel
     int W = 0, H = 0;  // footprint bounds (columns, rows)

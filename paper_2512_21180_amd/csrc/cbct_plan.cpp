@@ -109,36 +109,76 @@ TileBuild make_tiles(const cbct_geom *g, int TV)
     return tb;
 }
 
-// Panel footprint (columns, rows) of the support box of voxel ranges
-// [i0,i1] x [j0,j1] x [k0,k1] at angle th, in FP64, with the kernel's margins.
-void footprint(const cbct_geom_desc &d, double th, int i0, int i1, int j0, int j1, int k0, int k1,
-               int nt, int *W, int *H)
+// Window bounds of bricks 8 x 8 x bk staging `channels` channels per
+// element; ok when the window fits the LDS budget.  Every brick and angle
+// is evaluated: per (angle, brick column) the corner projections give the
+// column range and the extreme source-panel scales, and per brick layer the
+// row range follows from them (rows are linear in z for a fixed scale).
+// Both ranges are clipped to the panel as the kernel clips them, with the
+// kernel's margins plus one for FP32 rounding on each side.
+AdjPlan adjoint_plan(const cbct_geom *g, int bk, int channels, int NT, size_t budget)
 {
-    const double c = std::cos(th), s = std::sin(th);
+    const cbct_geom_desc &d = g->desc;
+    AdjPlan p{};
+    int W = 0, H = 0;
+    const int nbx = (d.nx + kBI - 1) / kBI, nby = (d.ny + kBJ - 1) / kBJ;
+    const int nbz = (d.nz + bk - 1) / bk;
     auto cx = [&](double i) { return d.origin_mm[0] + (i - 0.5 * (d.nx - 1)) * d.vx_mm; };
     auto cy = [&](double j) { return d.origin_mm[1] + (j - 0.5 * (d.ny - 1)) * d.vy_mm; };
     auto cz = [&](double k) { return d.origin_mm[2] + (k - 0.5 * (d.nz - 1)) * d.vz_mm; };
-    double xs[2] = {cx(i0) - d.vx_mm, cx(i1) + d.vx_mm};
-    double ys[2] = {cy(j0) - d.vy_mm, cy(j1) + d.vy_mm};
-    double zs[2] = {cz(k0) - d.vz_mm, cz(k1) + d.vz_mm};
-    double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
-    for (double x : xs)
-        for (double y : ys) {
-            double den = c * x + s * y - d.sid_mm;
-            double lam = -d.sdd_mm / den;
-            double u = (lam * (-s * x + c * y) - d.off_u_mm) / d.du_mm + 0.5 * (d.nu - 1);
-            umin = std::min(umin, u);
-            umax = std::max(umax, u);
-            for (double z : zs) {
-                double v = (lam * z - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
-                vmin = std::min(vmin, v);
-                vmax = std::max(vmax, v);
+    for (int a = 0; a < d.n_angles; ++a) {
+        const double c = std::cos(g->angles[a]), s = std::sin(g->angles[a]);
+        for (int by = 0; by < nby; ++by)
+            for (int bx = 0; bx < nbx; ++bx) {
+                const int i0 = bx * kBI, i1 = std::min(i0 + kBI, d.nx) - 1;
+                const int j0 = by * kBJ, j1 = std::min(j0 + kBJ, d.ny) - 1;
+                const double xs[2] = {cx(i0) - d.vx_mm, cx(i1) + d.vx_mm};
+                const double ys[2] = {cy(j0) - d.vy_mm, cy(j1) + d.vy_mm};
+                double umin = 1e300, umax = -1e300, lmin = 1e300, lmax = -1e300;
+                for (double x : xs)
+                    for (double y : ys) {
+                        const double lam = -d.sdd_mm / (c * x + s * y - d.sid_mm);
+                        const double u =
+                            (lam * (-s * x + c * y) - d.off_u_mm) / d.du_mm + 0.5 * (d.nu - 1);
+                        umin = std::min(umin, u);
+                        umax = std::max(umax, u);
+                        lmin = std::min(lmin, lam);
+                        lmax = std::max(lmax, lam);
+                    }
+                const double u0 = std::max(std::floor(umin) - 2.0, 0.0);
+                const double u1 = std::min(std::ceil(umax) + 2.0, (double)(d.nu - 1));
+                if (u1 < u0)
+                    continue;
+                W = std::max(W, (int)(u1 - u0) + 1);
+                for (int bz = 0; bz < nbz; ++bz) {
+                    const int k0 = bz * bk, k1 = std::min(k0 + bk, d.nz) - 1;
+                    const double zl = cz(k0) - d.vz_mm, zh = cz(k1) + d.vz_mm;
+                    const double vmin =
+                        (std::min(lmin * zl, lmax * zl) - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
+                    const double vmax =
+                        (std::max(lmin * zh, lmax * zh) - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
+                    const double v0 = std::max(std::floor(vmin) - 3.0, 0.0);
+                    const double v1 = std::min(std::ceil(vmax) + 3.0, (double)(d.nv - 1));
+                    if (v1 >= v0)
+                        H = std::max(H, (int)(v1 - v0) + 1);
+                }
             }
-        }
-    // kernel: [floor(umin)-1, ceil(umax)+1] x [floor(vmin)-2, ceil(vmax)+2+nt],
-    // plus one for FP32 rounding on each side
-    *W = (int)(std::ceil(umax) - std::floor(umin)) + 3 + 2;
-    *H = (int)(std::ceil(vmax) - std::floor(vmin)) + 5 + nt + 2;
+    }
+    // a tap run never leaves the window (its start is clamped), so the
+    // window needs the brick's rows, or one run when that is taller
+    H = std::max(H, NT);
+    // the window is stored column-major with an odd column stride, so a row
+    // of lanes writing consecutive columns hits distinct LDS banks
+    int WS = H | 1;
+    size_t lds = (size_t)W * WS * channels * sizeof(float) + (size_t)W * 4 * sizeof(float);
+    if (W > 0 && lds <= budget && NT <= kMaxTaps) {
+        p.ok = true;
+        p.W = W;
+        p.H = H;
+        p.WS = WS;
+        p.NTmax = NT;
+    }
+    return p;
 }
 
 }  // namespace
@@ -187,36 +227,7 @@ void plan_host(cbct_geom *g)
     const double t_min = (d.sid_mm - R_sup) / d.sdd_mm;
     const double rvs = d.dv_mm / d.vz_mm;
     const int NT = adj_taps_rounded((int)std::floor(2.0 / (t_min * rvs)) + 3);
-    int W = 0, H = 0;
-    const int nbx = (d.nx + kBI - 1) / kBI, nby = (d.ny + kBJ - 1) / kBJ;
-    const int nbz = (d.nz + kBK - 1) / kBK;
-    // the widest window occurs at any height; the tallest in the top or
-    // bottom layer of bricks (perspective grows with |z|)
-    int zl[3] = {0, nbz / 2, nbz - 1};
-    for (int a = 0; a < d.n_angles; ++a)
-        for (int by = 0; by < nby; ++by)
-            for (int bx = 0; bx < nbx; ++bx)
-                for (int bz : zl) {
-                    int w, h;
-                    footprint(d, g->angles[a], bx * kBI, std::min(bx * kBI + kBI, d.nx) - 1,
-                              by * kBJ, std::min(by * kBJ + kBJ, d.ny) - 1, bz * kBK,
-                              std::min(bz * kBK + kBK, d.nz) - 1, NT, &w, &h);
-                    W = std::max(W, w);
-                    H = std::max(H, h);
-                }
-    W = std::min(W, d.nu + 4);
-    H = std::min(H, d.nv + NT + 8);
-    // the window is stored column-major with an odd column stride, so a row
-    // of lanes writing consecutive columns hits distinct LDS banks
-    int WS = H | 1;
-    size_t lds = (size_t)W * WS * sizeof(float) + (size_t)W * 4 * sizeof(float);
-    if (lds <= kAdjLdsBudget && NT <= kMaxTaps) {
-        g->adj.ok = true;
-        g->adj.W = W;
-        g->adj.H = H;
-        g->adj.WS = WS;
-        g->adj.NTmax = NT;
-    }
+    g->adj = adjoint_plan(g, kBK, 1, NT, kAdjLdsBudget);
 }
 
 }  // namespace cbct

@@ -185,15 +185,21 @@ def taps_rounded(nt):
     return 32
 
 
-def _adj_brick_check(h, bx, by, bz, angles):
+def _adj_plan(h, bk):
+    """(W, H, WS, NTmax) of the plan for bricks bk voxels deep."""
+    assert bk == 16
+    return h.info[6], h.info[7], h.info[8], h.info[9]
+
+
+def _adj_brick_check(h, bx, by, bz, angles, bk=16):
     g = h.g
     s = h.s
     nx, ny, nz, nu, nv = g["nx"], g["ny"], g["nz"], g["nu"], g["nv"]
-    W_, H_, WS, NTmax = h.info[6], h.info[7], h.info[8], h.info[9]
+    W_, H_, WS, NTmax = _adj_plan(h, bk)
     Kb, rvs, rv0, cv = s["Kb"], s["rvs"], s["rv0"], s["cv"]
     i0, i1 = bx * 8, min(bx * 8 + 8, nx) - 1
     j0, j1 = by * 8, min(by * 8 + 8, ny) - 1
-    k0, k1 = bz * 16, min(bz * 16 + 16, nz) - 1
+    k0, k1 = bz * bk, min(bz * bk + bk, nz) - 1
 
     def cx(i):
         return f32(s["ox"] + f32(f32(i) - f32(0.5) * f32(nx - 1)) * s["vx"])
@@ -231,11 +237,17 @@ def _adj_brick_check(h, bx, by, bz, angles):
         U1 = min(min(int(np.ceil(max(us))) + 1, nu - 1), U0 + W_ - 1)
         NT = taps_rounded(min(int(np.floor(f32(2.0) / f32(min(ts) * rvs))) + 3, NTmax))
         V0 = max(int(np.floor(min(vs_))) - 2, 0)
-        V1 = min(min(int(np.ceil(max(vs_))) + 2, nv - 1), V0 + H_ - NT - 1)
+        V1u = min(int(np.ceil(max(vs_))) + 2, nv - 1)
+        V1 = min(V1u, V0 + H_ - 1)
         if U0 > U1 or V0 > V1:
             # nothing of this brick may be visible at this angle
             continue
-        assert U1 - U0 + 1 <= W_ and V1 - V0 + 1 + NT <= H_ and H_ <= WS and WS % 2 == 1
+        # the plan's window holds the brick's rows (the clamp never cuts) and
+        # one run; a run never leaves it
+        assert V1 == V1u
+        Hs = max(V1 - V0 + 1, NT)
+        VS1 = max(V1 - NT + 1, V0)
+        assert U1 - U0 + 1 <= W_ and Hs <= H_ and H_ <= WS and WS % 2 == 1
         for i in range(i0, i1 + 1):
             for j in range(j0, j1 + 1):
                 for cls in (0, 1):
@@ -272,9 +284,10 @@ def _adj_brick_check(h, bx, by, bz, angles):
                             vB = f32(rt * inv_rvs)
                             vA = fma32(fma32(f32(-1.0) - Kb, rt, -rv0), inv_rvs, cv)
                             vf = fma32(f32(kk), vB, vA)
-                            vstart = min(max(int(np.floor(vf)) - 1, V0), V1)
-                            assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)), \
-                                (a, i, j, kk, u, rows_sup, vstart, NT)
+                            vstart = min(max(int(np.floor(vf)) - 1, V0), VS1)
+                            assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)
+                                          & (rows_sup <= V1)), \
+                                (a, i, j, kk, u, rows_sup, vstart, NT, V1)
                             checked += len(rows_sup)
     return checked
 
@@ -291,9 +304,53 @@ def test_adjoint_windows_cover_every_weight(hosts, name):
     angs = np.unique(np.concatenate([rng.choice(na, min(na, 6), replace=False),
                                      [0, na // 8, na // 4 + 1]]))
     total = 0
-    for _ in range(n_b):
-        b = (int(rng.integers(nbx)), int(rng.integers(nby)), int(rng.integers(nbz)))
-        total += _adj_brick_check(h, *b, angles=[int(x) % na for x in angs])
-    # the central brick is always seen
-    total += _adj_brick_check(h, nbx // 2, nby // 2, nbz // 2, angles=[int(x) % na for x in angs])
+    for bk in (16,):
+        nbz = -(-g["nz"] // bk)
+        for _ in range(n_b):
+            b = (int(rng.integers(nbx)), int(rng.integers(nby)), int(rng.integers(nbz)))
+            total += _adj_brick_check(h, *b, angles=[int(x) % na for x in angs], bk=bk)
+        # the central brick is always seen
+        total += _adj_brick_check(h, nbx // 2, nby // 2, nbz // 2,
+                                  angles=[int(x) % na for x in angs], bk=bk)
     assert total > 0
+
+
+@pytest.mark.parametrize("name", ["ragged", "c1", "c4", "c2", "steep_angles"])
+def test_adjoint_window_bound_holds_for_every_brick(hosts, name):
+    """The planned window height bounds the clipped window of every brick
+    (all layers, FP32 as in the kernel) at a dozen angles: the kernel's row
+    clamp V0 + H - 1 never cuts a brick's rows."""
+    h = hosts[name]
+    g, s = h.g, h.s
+    nx, ny, nz, nv = g["nx"], g["ny"], g["nz"], g["nv"]
+    na = g["n_angles"]
+    inv_dv = f32(f32(1.0) / s["dv"])
+    for bk in (16,):
+        _, H_, _, _ = _adj_plan(h, bk)
+        for a in np.linspace(0, na - 1, 12).astype(int):
+            c_, s_ = h.ang_cs[a]
+            for bx in range(-(-nx // 8)):
+                for by in range(-(-ny // 8)):
+                    i0, i1 = bx * 8, min(bx * 8 + 8, nx) - 1
+                    j0, j1 = by * 8, min(by * 8 + 8, ny) - 1
+                    lams = []
+                    for i in (i0, i1):
+                        for j in (j0, j1):
+                            x = f32(f32(s["ox"] + f32(f32(i) - f32(0.5) * f32(nx - 1)) * s["vx"])
+                                    + (s["vx"] if i == i1 else -s["vx"]))
+                            y = f32(f32(s["oy"] + f32(f32(j) - f32(0.5) * f32(ny - 1)) * s["vy"])
+                                    + (s["vy"] if j == j1 else -s["vy"]))
+                            den = fma32(c_, x, fma32(s_, y, -s["sid"]))
+                            lams.append(f32(-s["sdd"] * f32(f32(1.0) / den)))
+                    for bz in range(-(-nz // bk)):
+                        k0, k1 = bz * bk, min(bz * bk + bk, nz) - 1
+                        zl = f32(f32(s["oz"] + f32(f32(k0) - f32(0.5) * f32(nz - 1)) * s["vz"])
+                                 - s["vz"])
+                        zh = f32(f32(s["oz"] + f32(f32(k1) - f32(0.5) * f32(nz - 1)) * s["vz"])
+                                 + s["vz"])
+                        vv = [fma32(fma32(l, z, -s["off_v"]), inv_dv, s["cv"])
+                              for l in lams for z in (zl, zh)]
+                        V0 = max(int(np.floor(min(vv))) - 2, 0)
+                        V1u = min(int(np.ceil(max(vv))) + 2, nv - 1)
+                        if V1u >= V0:
+                            assert V1u - V0 + 1 <= H_, (name, bk, a, bx, by, bz, V0, V1u, H_)
