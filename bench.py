@@ -7,6 +7,10 @@ FP32, on a seeded synthetic phantom already resident in HBM.  Throughput is
 (S_A + S_AT) / time in Gsamples/s, where S is the library's sample count
 (ray-plane pairs with non-empty support; A^T applies the same samples).
 
+Also measured (key "recon"): the metric's second half, seconds to a fixed
+PSNR for the learned primal-dual net against CGLS on one held-out phantom
+(see recon_comparison).
+
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
 GPU only.
 """
@@ -105,6 +109,31 @@ def record_traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
     return rec
 
 
+def recon_comparison(seed=50_000):
+    """Second half of the metric: seconds to a fixed PSNR, learned net vs
+    CGLS, on one held-out phantom of the same case (Poisson I0 = 1e5).  The
+    fixed PSNR is the best CGLS reaches in 50 iterations; both methods run on
+    the same FP32 projector pair with the data in HBM, timed per iteration
+    with HIP events.  Weights: the committed multiscale net (8 iterations,
+    resolutions 1/4, 1/4, 1/4, 1/2, 1/2, 1/2, 1, 1, FDK start)."""
+    from paper_2512_21180_amd import compare
+
+    S = compare.Setup(compare.DEFAULT_WEIGHTS)
+    r = compare.compare_one(S, seed, log=lambda m: print(m, file=sys.stderr, flush=True))
+    return {
+        "fixed_psnr_db": r["target_psnr_db"],
+        "cgls_s": r["cgls_time_to_target_s"],
+        "learned_s": r["learned_time_to_target_s"],
+        "cgls_iterations": r["cgls_best_iter"],
+        "learned_final_psnr_db": r["learned_psnr_db"][-1],
+        "learned_total_s": r["learned_time_s"][-1],
+        "blocks_zeroed_psnr_db": r["zero_block_psnr_db"][-1],
+        "fdk_psnr_db": r["fdk_psnr_db"],
+        "phantom_seed": seed,
+        "net": {"iterations": S.net.n_iter, "scales": list(S.net.scales), "init": S.net.init},
+    }
+
+
 def cpu_baseline(g, n_angles=72):
     """The FP64 oracle on the same geometry restricted to n_angles of its
     angles (every n/n_angles-th), forward then adjoint."""
@@ -141,6 +170,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recon", action="store_true",
+                    help="skip the reconstruction comparison (learned net vs CGLS)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device-to-device copy (for counter calibration)")
     ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -148,7 +179,7 @@ def main():
     args = ap.parse_args()
     if args.record_traffic:
         cmd = ("timeout -s KILL 120 rocprofv3 --pmc {c} -f csv -d {d} -o run -- python3 -u "
-               "bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-calibration")
+               "bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-recon --copy-calibration")
         f_csv, w_csv = args.record_traffic
         rec = record_traffic(f_csv, w_csv,
                              cmd.format(c="FETCH_SIZE", d=os.path.dirname(f_csv)),
@@ -238,6 +269,8 @@ def main():
         for _ in range(2):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if not args.no_recon:
+        out["recon"] = recon_comparison()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g)
     print(json.dumps(out), flush=True)

@@ -18,13 +18,16 @@ PSNR over the full field of view (voxels seen in at least half of the
 projections): 10 log10(max(x_true)^2 / mean((x - x_true)^2)) in units of
 0.02 /mm.
 
-    python -m paper_2512_21180_amd.compare --weights weights.pt --json out.json
+    python -m paper_2512_21180_amd.compare [--weights weights.pt] --json out.json
+
+(default weights: the committed multiscale FDK-start net, `weights/`).
 """
 from __future__ import annotations
 
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -63,77 +66,92 @@ def timed(run, n_events):
     return [ev0.elapsed_time(e) * 1e-3 for e in evs]
 
 
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                               "lpd_c5_multiscale_fdk.pt")
+
+
+class Setup:
+    """Geometry, FoV tensor, operator norm, net and PSNR helper of the
+    clinical case (per-geometry constants, computed once)."""
+
+    def __init__(self, weights: str):
+        self.g = W.C2
+        self.geo = cbct.Geometry(self.g)
+        self.V = torch.tensor(cbct.fov_fraction(self.g), device="cuda")
+        self.L = solvers.opnorm(self.geo, iters=50, seed=0)
+        self.net = load(weights)
+        self.model = learned.LearnedPD(self.net, self.geo, self.V, self.L)
+        n = self.geo.vol_shape[0] * self.geo.vol_shape[1] * self.geo.vol_shape[2]
+        self.psnr = PSNR(self.V, n)
+
+
+def compare_one(S: Setup, seed: int, I0: float = 1e5, K: int = 50, log=print) -> dict:
+    """One test phantom: CGLS (K iterations) and the learned net, each timed
+    per iteration and scored per iterate; target = CGLS's best PSNR."""
+    geo, model, psnr, L, net = S.geo, S.model, S.psnr, S.L, S.net
+    t0 = time.time()
+    x_mu = torch.tensor(W.phantom_c2(S.g, seed)[0], dtype=torch.float32, device="cuda")
+    y, xt = simulate_pair(geo, x_mu, I0, seed=seed, L=L)
+    peak = float((xt * psnr.fov).max())
+    log(f"[compare] phantom seed {seed} ready in {time.time() - t0:.1f} s")
+    # CGLS on the same normalised data: the iterates solve (A / L) x = y
+    y_cg = y.clone()
+    cbct.axpby(y_cg, L, y_cg, 0.0, y_cg)             # A x = L y
+    t_cg = timed(lambda mark: solvers.cgls(geo, y_cg, K, callback=lambda k, x: mark(k)), K)
+    ps_cg = []
+    solvers.cgls(geo, y_cg, K, callback=lambda k, x: ps_cg.append(psnr(x, xt, peak)))
+    log(f"[compare]   CGLS best {max(ps_cg):.2f} dB at iteration "
+        f"{int(np.argmax(ps_cg)) + 1} ({t_cg[int(np.argmax(ps_cg))]:.3f} s); "
+        f"{K} iterations {t_cg[-1]:.3f} s")
+    # FDK (offset-detector weights) on the same data: A x = L y
+    t_fdk = timed(lambda mark: (cbct.fdk(geo, y_cg), mark(1)), 1)[0]
+    ps_fdk = psnr(cbct.fdk(geo, y_cg), xt, peak)
+    ps_fdk_h = psnr(cbct.fdk(geo, y_cg, window="hann"), xt, peak)
+    n = net.n_iter
+    t_ln = timed(lambda mark: model.reconstruct(y, callback=lambda i, x: mark(i)), n)
+    ps_ln = []
+    model.reconstruct(y, callback=lambda i, x: ps_ln.append(psnr(x, xt, peak)))
+    ps_zero = []
+    model.reconstruct(y, zero_blocks=True, callback=lambda i, x: ps_zero.append(psnr(x, xt, peak)))
+    target = max(ps_cg)
+
+    def first(ps, ts):
+        for v, t in zip(ps, ts):
+            if v >= target:
+                return t
+        return None
+
+    r = {"seed": seed, "target_psnr_db": round(target, 3),
+         "cgls_best_iter": int(np.argmax(ps_cg)) + 1,
+         "cgls_psnr_db": [round(v, 3) for v in ps_cg],
+         "cgls_time_s": [round(v, 4) for v in t_cg],
+         "learned_psnr_db": [round(v, 3) for v in ps_ln],
+         "learned_time_s": [round(v, 4) for v in t_ln],
+         "zero_block_psnr_db": [round(v, 3) for v in ps_zero],
+         "fdk_psnr_db": round(ps_fdk, 3), "fdk_hann_psnr_db": round(ps_fdk_h, 3),
+         "fdk_time_s": round(t_fdk, 4),
+         "cgls_time_to_target_s": first(ps_cg, t_cg),
+         "learned_time_to_target_s": first(ps_ln, t_ln)}
+    log(f"[compare]   FDK {ps_fdk:.2f} dB, Hann {ps_fdk_h:.2f} dB ({t_fdk:.3f} s)")
+    log(f"[compare]   learned {ps_ln[-1]:.2f} dB after {n} iterations ({t_ln[-1]:.3f} s); "
+        f"zero-block net {ps_zero[-1]:.2f} dB; time to {target:.2f} dB: CGLS "
+        f"{r['cgls_time_to_target_s']} s, learned {r['learned_time_to_target_s']} s")
+    return r
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--weights", required=True)
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--phantoms", type=int, default=3)
     ap.add_argument("--cgls-iters", type=int, default=50)
     ap.add_argument("--I0", type=float, default=1e5)
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    g = W.C2
-    geo = cbct.Geometry(g)
-    V = torch.tensor(cbct.fov_fraction(g), device="cuda")
-    L = solvers.opnorm(geo, iters=50, seed=0)
-    net = load(args.weights)
-    model = learned.LearnedPD(net, geo, V, L)
-    psnr = PSNR(V, max(geo.vol_shape[0] * geo.vol_shape[1] * geo.vol_shape[2], 1))
-    K = args.cgls_iters
-    results = []
-    for p in range(args.phantoms):
-        seed = 50_000 + p
-        t0 = time.time()
-        x_mu = torch.tensor(W.phantom_c2(g, seed)[0], dtype=torch.float32, device="cuda")
-        y, xt = simulate_pair(geo, x_mu, args.I0, seed=seed, L=L)
-        peak = float((xt * psnr.fov).max())
-        print(f"[compare] phantom {p} (seed {seed}) ready in {time.time() - t0:.1f} s",
-              flush=True)
-        # CGLS on the same normalised data: the iterates solve (A / L) x = y
-        y_cg = y.clone()
-        cbct.axpby(y_cg, L, y_cg, 0.0, y_cg)             # A x = L y
-        t_cg = timed(lambda mark: solvers.cgls(geo, y_cg, K, callback=lambda k, x: mark(k)), K)
-        ps_cg = []
-        solvers.cgls(geo, y_cg, K, callback=lambda k, x: ps_cg.append(psnr(x, xt, peak)))
-        print(f"[compare]   CGLS best {max(ps_cg):.2f} dB at iteration "
-              f"{int(np.argmax(ps_cg)) + 1} ({t_cg[int(np.argmax(ps_cg))]:.3f} s); "
-              f"{K} iterations {t_cg[-1]:.3f} s", flush=True)
-        # FDK (offset-detector weights) on the same data: A x = L y
-        t_fdk = timed(lambda mark: (cbct.fdk(geo, y_cg), mark(1)), 1)[0]
-        ps_fdk = psnr(cbct.fdk(geo, y_cg), xt, peak)
-        ps_fdk_h = psnr(cbct.fdk(geo, y_cg, window="hann"), xt, peak)
-        n = net.n_iter
-        t_ln = timed(lambda mark: model.reconstruct(y, callback=lambda i, x: mark(i)), n)
-        ps_ln = []
-        model.reconstruct(y, callback=lambda i, x: ps_ln.append(psnr(x, xt, peak)))
-        ps_zero = []
-        model.reconstruct(y, zero_blocks=True,
-                          callback=lambda i, x: ps_zero.append(psnr(x, xt, peak)))
-        target = max(ps_cg)
-
-        def first(ps, ts):
-            for v, t in zip(ps, ts):
-                if v >= target:
-                    return t
-            return None
-
-        r = {"seed": seed, "target_psnr_db": round(target, 3),
-             "cgls_best_iter": int(np.argmax(ps_cg)) + 1,
-             "cgls_psnr_db": [round(v, 3) for v in ps_cg],
-             "cgls_time_s": [round(v, 4) for v in t_cg],
-             "learned_psnr_db": [round(v, 3) for v in ps_ln],
-             "learned_time_s": [round(v, 4) for v in t_ln],
-             "zero_block_psnr_db": [round(v, 3) for v in ps_zero],
-             "fdk_psnr_db": round(ps_fdk, 3), "fdk_hann_psnr_db": round(ps_fdk_h, 3),
-             "fdk_time_s": round(t_fdk, 4),
-             "cgls_time_to_target_s": first(ps_cg, t_cg),
-             "learned_time_to_target_s": first(ps_ln, t_ln)}
-        print(f"[compare]   FDK {ps_fdk:.2f} dB, Hann {ps_fdk_h:.2f} dB ({t_fdk:.3f} s)", flush=True)
-        print(f"[compare]   learned {ps_ln[-1]:.2f} dB after {n} iterations ({t_ln[-1]:.3f} s); "
-              f"zero-block net {ps_zero[-1]:.2f} dB; time to {target:.2f} dB: CGLS "
-              f"{r['cgls_time_to_target_s']} s, learned {r['learned_time_to_target_s']} s",
-              flush=True)
-        results.append(r)
+    S = Setup(args.weights)
+    results = [compare_one(S, 50_000 + p, args.I0, args.cgls_iters,
+                           log=lambda m: print(m, flush=True)) for p in range(args.phantoms)]
+    net = S.net
     summary = {
         "workload": "256^3 @2 mm, 360 angles, 512^2 @0.8 mm, 115 mm offset; Poisson I0 "
                     f"{args.I0:g}; {args.phantoms} test phantoms",
