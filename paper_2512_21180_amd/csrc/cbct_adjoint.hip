@@ -187,7 +187,8 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *co
 
     const int bx = b % A.nbx, by = (b / A.nbx) % A.nby, bz = b / (A.nbx * A.nby);
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the wave index is uniform (scalar registers for its row and layer indices)
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int i = bx * kBI + (lane & 7), j = by * kBJ + (lane >> 3);
     const int k0 = bz * kBK + w * KV;
     const int ic = min(i, g.nx - 1), jc = min(j, g.ny - 1);
