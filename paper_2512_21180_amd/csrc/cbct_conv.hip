@@ -8,8 +8,8 @@
 // K = 27 taps x 16 input channels, two taps per v_mfma_f32_16x16x32_bf16
 // (14 MFMAs per tile).  Lane l supplies, for MFMA p, 8 input channels
 // (8 (l/16) % 16 ..) of tap 2p + l/32 at position x0 + l%16: one 16-byte
-// load of the channel-last activations.  The weights stay in registers for
-// the whole wave.  The result tile (lane l holds rows 4 (l/16) .. +3 of
+// LDS read of the staged channel-last activations.  The weights are staged
+// once per workgroup and stay in registers over the wave's four tiles.  The result tile (lane l holds rows 4 (l/16) .. +3 of
 // column l%16) goes through the epilogue: bias, LeakyReLU derivative mask,
 // LeakyReLU, then bf16 channel-last and/or FP32 channel-first stores.
 //
@@ -76,8 +76,7 @@ __global__ void __launch_bounds__(kT) k_pack16(size_t S, int n_in, CPtrList in, 
 // ---- conv3 -------------------------------------------------------------------
 
 struct ConvArgs {
-    int nz, ny, nx, nxt;          // grid and x tiles per row
-    long n_tiles;                 // nz * ny * nxt
+    int nz, ny, nx;               // grid
     const uint16_t *x, *w;
     const float *bias;
     const uint16_t *mask;
@@ -89,82 +88,118 @@ struct ConvArgs {
     PtrList y_cf;
 };
 
+// A workgroup computes an output block of one z plane, kRows rows and 64
+// positions along x (4 x-tiles of 16): wave w takes row y0 + w and its four
+// tiles.  The block's input halo (3 planes x (kRows + 2) rows x 66 positions
+// x 16 channels) and the layer's weights are staged in LDS once; each MFMA's
+// A operand is one 16-byte LDS read per lane (channels 0-7 and 8-15 in
+// separate planes, so the 16 lanes of a group read consecutive words).
+constexpr int kRows = 4, kBX = 64;
+constexpr int kHX = kBX + 2, kHY = kRows + 2, kHP = 3 * kHY * kHX;   // halo positions
+
 __global__ void __launch_bounds__(kT) k_conv3(ConvArgs A)
 {
-    const int lane = threadIdx.x & 63;
-    const long tile = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= A.n_tiles)
-        return;   // whole wavefront
-    const int xt = (int)(tile % A.nxt);
-    const long row = tile / A.nxt;
-    const int y = (int)(row % A.ny), z = (int)(row / A.ny);
-    const int x0 = xt * 16;
+    __shared__ uint4 halo[2][kHP];            // [channel half][position] 8 bf16 each
+    __shared__ uint4 wsh[27 * 16 * 2];        // [tap][cout][channel half]
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nbx = (A.nx + kBX - 1) / kBX, nby = (A.ny + kRows - 1) / kRows;
+    const int bx = blockIdx.x % nbx;
+    const int by = (blockIdx.x / nbx) % nby;
+    const int z = blockIdx.x / (nbx * nby);
+    const int x0 = bx * kBX, y0 = by * kRows;
+
+    // ---- stage the weights: wsh[t][co][h] = 8 input channels 8h.. of w'[t][co]
+    for (int e = tid; e < 27 * 16 * 2; e += kT) {
+        const int t = e >> 5, co = (e >> 1) & 15, h = e & 1;
+        uint4 q;
+        if (!A.transpose_w) {
+            q = *reinterpret_cast<const uint4 *>(A.w + ((size_t)t * 16 + co) * 16 + 8 * h);
+        } else {
+            // w'[t][co][ci] = w[26 - t][ci][co]
+            uint16_t v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v[j] = A.w[((size_t)(26 - t) * 16 + 8 * h + j) * 16 + co];
+            q = make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                           (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16));
+        }
+        wsh[e] = q;
+    }
+    // ---- stage the input halo (zero outside the grid)
+    for (int e = tid; e < 2 * kHP; e += kT) {
+        const int hp = e >> 1, h = e & 1;
+        const int hx = hp % kHX, hy = (hp / kHX) % kHY, hz = hp / (kHX * kHY);
+        const int xx = x0 - 1 + hx, yy = y0 - 1 + hy, zz = z - 1 + hz;
+        uint4 q = make_uint4(0u, 0u, 0u, 0u);
+        if ((unsigned)xx < (unsigned)A.nx && (unsigned)yy < (unsigned)A.ny &&
+            (unsigned)zz < (unsigned)A.nz) {
+            const size_t pos = ((size_t)zz * A.ny + yy) * A.nx + xx;
+            q = *reinterpret_cast<const uint4 *>(A.x + pos * 16 + 8 * h);
+        }
+        halo[h][hp] = q;
+    }
+    __syncthreads();
+
+    const int y = y0 + w;
+    if (y >= A.ny)
+        return;   // whole wave; no barrier follows
 
     const int m = lane & 15;          // position within the tile (A rows) / output channel (B cols)
     const int kb = lane >> 4;         // k block: tap 2p + (kb >> 1), channels 8 (kb & 1) ..
-    const int c0 = (kb & 1) * 8;
+    const int hh = kb & 1;
 
-    // weights: B[k][n] for n = m (output channel), 8 input channels from c0
+    // weights: B[k][n] for n = m (output channel), 8 input channels of half hh
     bf16x8 wr[14];
 #pragma unroll
     for (int p = 0; p < 14; ++p) {
         const int t = 2 * p + (kb >> 1);
         bf16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (t < 27) {
-            if (!A.transpose_w) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(A.w + ((size_t)t * 16 + m) * 16 + c0);
-                v = __builtin_bit_cast(bf16x8, q);
-            } else {
-                // w'[t][co = m][ci] = w[26 - t][ci][m]
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    v[j] = (short)A.w[((size_t)(26 - t) * 16 + c0 + j) * 16 + m];
-            }
-        }
+        if (t < 27)
+            v = __builtin_bit_cast(bf16x8, wsh[(t * 16 + m) * 2 + hh]);
         wr[p] = v;
     }
-
-    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    const int xs = x0 + m;
-#pragma unroll
-    for (int p = 0; p < 14; ++p) {
-        const int t = 2 * p + (kb >> 1);
-        bf16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (t < 27) {
-            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-            const int zz = z + dz, yy = y + dy, xx = xs + dx;
-            if ((unsigned)zz < (unsigned)A.nz && (unsigned)yy < (unsigned)A.ny &&
-                (unsigned)xx < (unsigned)A.nx) {
-                const size_t pos = ((size_t)zz * A.ny + yy) * A.nx + xx;
-                const uint4 q = *reinterpret_cast<const uint4 *>(A.x + pos * 16 + c0);
-                a = __builtin_bit_cast(bf16x8, q);
-            }
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wr[p], acc, 0, 0, 0);
-    }
-
-    // epilogue: lane holds rows 4 kb + i (positions), column m (output channel)
     const int co = m;
     const float b = A.bias ? A.bias[co] : 0.0f;
+
+    for (int tx = 0; tx < kBX / 16; ++tx) {
+        const int xt0 = x0 + 16 * tx;
+        if (xt0 >= A.nx)
+            break;   // uniform
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int xo = x0 + 4 * kb + i;
-        if (xo >= A.nx)
-            continue;
-        const size_t pos = ((size_t)z * A.ny + y) * A.nx + xo;
-        float v = acc[i] + b;
-        if (A.mask) {
-            const uint16_t h = A.mask[pos * 16 + co];
-            const bool positive = !(h & 0x8000u) && (h & 0x7fffu);
-            v = positive ? v : A.slope * v;
+        for (int p = 0; p < 14; ++p) {
+            const int t = 2 * p + (kb >> 1);
+            bf16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (t < 27) {
+                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;   // offsets + 1
+                const int hp = (dz * kHY + (w + dy)) * kHX + 16 * tx + m + dx;
+                a = __builtin_bit_cast(bf16x8, halo[hh][hp]);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wr[p], acc, 0, 0, 0);
         }
-        if (A.act)
-            v = v > 0.0f ? v : A.slope * v;
-        if (A.y_cl)
-            A.y_cl[pos * 16 + co] = f2bf(v);
-        if (co < A.n_cf) {
-            float *dst = A.y_cf.p[co] + pos;
-            *dst = A.accumulate ? fmaf(A.alpha, v, *dst) : v;
+        // epilogue: lane holds rows 4 kb + i (positions), column m (output channel)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int xo = xt0 + 4 * kb + i;
+            if (xo >= A.nx)
+                continue;
+            const size_t pos = ((size_t)z * A.ny + y) * A.nx + xo;
+            float v = acc[i] + b;
+            if (A.mask) {
+                const uint16_t hm = A.mask[pos * 16 + co];
+                const bool positive = !(hm & 0x8000u) && (hm & 0x7fffu);
+                v = positive ? v : A.slope * v;
+            }
+            if (A.act)
+                v = v > 0.0f ? v : A.slope * v;
+            if (A.y_cl)
+                A.y_cl[pos * 16 + co] = f2bf(v);
+            if (co < A.n_cf) {
+                float *dst = A.y_cf.p[co] + pos;
+                *dst = A.accumulate ? fmaf(A.alpha, v, *dst) : v;
+            }
         }
     }
 }
@@ -346,8 +381,6 @@ extern "C" cbct_status cbct_conv3(int nz, int ny, int nx, const uint16_t *x, con
     A.nz = nz;
     A.ny = ny;
     A.nx = nx;
-    A.nxt = (nx + 15) / 16;
-    A.n_tiles = (long)nz * ny * A.nxt;
     A.x = x;
     A.w = w;
     A.bias = bias;
@@ -364,7 +397,7 @@ extern "C" cbct_status cbct_conv3(int nz, int ny, int nx, const uint16_t *x, con
             return CBCT_E_NULL;
         A.y_cf.p[c] = y_cf[c];
     }
-    const long blocks = (A.n_tiles + 3) / 4;
+    const long blocks = (long)nz * ((ny + kRows - 1) / kRows) * ((nx + kBX - 1) / kBX);
     if (blocks >= 0x7fffffffL)
         return CBCT_E_SHAPE;
     hipLaunchKernelGGL(k_conv3, dim3((unsigned)blocks), dim3(kT), 0, (hipStream_t)stream, A);
