@@ -340,18 +340,38 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *co
     }
 }
 
+// Workgroups are dealt to the 8 XCDs round robin (XCD = id % 8).  XCD xc
+// takes the brick rows by = xc, xc + 8, ... (every z layer of them, so each
+// XCD holds an even share of cheap and costly bricks), in the order bx, bz,
+// row: workgroups resident together on one XCD are neighbouring bricks whose
+// panel windows overlap in its L2 (adjoint 33 -> 27 ms for the clinical
+// case; a contiguous brick range per XCD unbalances the XCDs, 71 ms).
+// Slot li of XCD xc -> brick index, or -1 for the padding slots.
+__device__ inline int brick_of_slot(const BrickArgs &A, int xc, int li)
+{
+    const int plane = A.nbx * A.nbz;
+    const int by = xc + 8 * (li / plane);
+    if (by >= A.nby)
+        return -1;
+    const int bz = (li % plane) / A.nbx, bx = li % A.nbx;
+    return (bz * A.nby + by) * A.nbx + bx;
+}
+
+// Slots per XCD of one case (padded so that every XCD has the same count).
+__host__ __device__ inline int slots_per_xcd(const BrickArgs &A)
+{
+    return A.nbx * A.nbz * ((A.nby + 7) / 8);
+}
+
 template <class SS, class VS>
 __global__ void __launch_bounds__(kThreads)
 adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
               typename VS::T *__restrict__ vol)
 {
     extern __shared__ float lds[];
-    // Plain brick order: workgroups are dealt to the 8 XCDs round robin, so
-    // every XCD gets an even share of the cheap bricks (outside the cone at
-    // most angles) and the costly ones.  (A contiguous brick range per XCD
-    // shares more panel windows in L2 but leaves some XCDs idle: 71 ms
-    // against 51 ms for the clinical case.)
-    const int b = blockIdx.x;
+    const int b = brick_of_slot(A, blockIdx.x & 7, blockIdx.x >> 3);
+    if (b < 0)
+        return;
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
@@ -370,7 +390,7 @@ struct AdjCase {
 
 struct BatchAdjArgs {
     int n_cases, n_items;
-    int first[kMaxBatch + 1];
+    int first[kMaxBatch + 1];   // first slot (per XCD) of each case
     AdjCase c[kMaxBatch];
 };
 
@@ -379,16 +399,19 @@ __global__ void __launch_bounds__(kThreads)
 adjoint_batch(BatchAdjArgs B)
 {
     extern __shared__ float lds[];
-    // one item per workgroup, in plain order as in adjoint_brick; the
-    // hardware dispatcher balances the uneven items
-    const int item = blockIdx.x;
+    // one item per workgroup; per XCD the slots of case 0, then case 1, ...,
+    // each case's slots mapped to bricks as in adjoint_brick
+    const int xc = blockIdx.x & 7, li = blockIdx.x >> 3;
     int cs = 0;
-    while (cs + 1 < B.n_cases && item >= B.first[cs + 1])
+    while (cs + 1 < B.n_cases && li >= B.first[cs + 1])
         ++cs;
     const AdjCase &C = B.c[cs];
+    const int b = brick_of_slot(C.A, xc, li - B.first[cs]);
+    if (b < 0)
+        return;
     const typename SS::T *ys[1] = {(const typename SS::T *)C.sino};
     typename VS::T *vs[1] = {(typename VS::T *)C.vol};
-    gather_brick<SS, VS, 1, kKV1>(C.A, item - B.first[cs], ys, vs, 1, lds);
+    gather_brick<SS, VS, 1, kKV1>(C.A, b, ys, vs, 1, lds);
 }
 
 }  // namespace
@@ -409,7 +432,7 @@ hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *
                                 hipStream_t s)
 {
     BrickArgs A = brick_args(g, p, 4 * kKV1);
-    dim3 grid(A.nbx * A.nby * A.nbz, channels), block(kThreads);
+    dim3 grid(8 * slots_per_xcd(A), channels), block(kThreads);
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
@@ -430,12 +453,12 @@ hipError_t launch_adjoint_batch(int n, const cbct_geom *const *gs, const void *c
         const cbct_geom *g = gs[i];
         B.first[i] = items;
         B.c[i] = AdjCase{brick_args(g->dev, g->adj, 4 * kKV1), sinos[i], vols[i]};
-        items += B.c[i].A.nbx * B.c[i].A.nby * B.c[i].A.nbz;
+        items += slots_per_xcd(B.c[i].A);
         lds = std::max(lds, brick_lds(g->adj, 1));
     }
     B.first[n] = items;
     B.n_items = items;
-    const int grid = items;
+    const int grid = 8 * items;
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
