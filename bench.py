@@ -13,9 +13,21 @@ PSNR for the learned primal-dual net against CGLS on one held-out phantom
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
 GPU only.
+
+`--workload` selects another case for the same measurement (the default is
+the clinical-size FP32 case above; the others skip the reconstruction
+comparison and the CPU baseline):
+  c2-bf16  the clinical-size case with BF16 volume and sinogram storage;
+  c1       64^3 at 4 mm, 64 angles, 128^2 panel at 3.2 mm, FP32;
+  c3       twelve heterogeneous cases (96^3..256^3, 2-4 mm, 90-360 angles,
+           256^2..512^2 panels) in one batched launch per operator, BF16
+           storage, FP32 accumulation;
+  c4       a batch of four 128^3 volumes at 2 mm, 180 angles, 256^2 panel at
+           1.6 mm with the 115 mm offset, FP32, one batched launch per operator.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -164,11 +176,127 @@ def cpu_baseline(g, n_angles=72):
     }
 
 
+WORKLOADS = {
+    "c2-bf16": "256^3 @2 mm volume, 360 angles over 2 pi, 512^2 panel @0.8 mm, 115 mm lateral "
+               "offset; 50-ellipsoid phantom in a 300 mm body cylinder; BF16 volume and sinogram "
+               "storage, FP32 accumulation; A + A^T",
+    "c1": "64^3 @4 mm volume, 64 angles over 2 pi, 128^2 panel @3.2 mm, no offset; 1-10 "
+          "ellipsoids; FP32 A + A^T",
+    "c3": "12 heterogeneous cases (96^3..256^3 at 2-4 mm, 90-360 angles, 256^2..512^2 panels, "
+          "half with the 115 mm offset) in one batched launch per operator; BF16 storage, FP32 "
+          "accumulation; A + A^T",
+    "c4": "batch of 4 volumes 128^3 @2 mm, 180 angles over 2 pi, 256^2 panel @1.6 mm, 115 mm "
+          "lateral offset, one batched launch per operator; FP32 A + A^T",
+}
+
+
+def secondary_workload(name, steps, warmup):
+    """Time A and A^T on one of the other cases.  Single cases go through
+    cbct_forward/cbct_adjoint, batches through cbct_batch_forward/adjoint (one
+    launch per operator).  Throughput is 2 x the summed sample counts over the
+    wall time of the timed steps; the roofline is that of the slower operator,
+    as for the default case."""
+    import torch
+    from paper_2512_21180_amd import cbct
+    from paper_2512_21180_amd import workloads as W
+
+    if name in ("c2-bf16", "c1"):
+        g = W.C2 if name == "c2-bf16" else W.C1
+        x_host = W.phantom_c2(g, 2025)[0] if name == "c2-bf16" else W.phantom_c1(g, 0)[0]
+        dt = torch.bfloat16 if name == "c2-bf16" else torch.float32
+        geos, vols = [cbct.Geometry(g)], [torch.tensor(x_host, device="cuda").to(dt)]
+        dtype = "bf16" if name == "c2-bf16" else "f32"
+    elif name == "c3":
+        gs = W.c3_geometries()
+        geos = [cbct.Geometry(g) for g in gs]
+        vols = [torch.tensor(W.phantom_c3(g, 1000 + i)[0], device="cuda").to(torch.bfloat16)
+                for i, g in enumerate(gs)]
+        dt, dtype = torch.bfloat16, "bf16"
+    else:
+        geo = cbct.Geometry(W.C4)
+        geos = [geo] * 4
+        vols = [torch.tensor(W.phantom_c1(W.C4, 4000 + i)[0], device="cuda").to(torch.float32)
+                for i in range(4)]
+        dt, dtype = torch.float32, "f32"
+    S = sum(g.sample_count() for g in geos)
+    sinos = [torch.empty(g.sino_shape, dtype=dt, device="cuda") for g in geos]
+    backs = [torch.empty(g.vol_shape, dtype=dt, device="cuda") for g in geos]
+
+    def fwd():
+        if len(geos) == 1:
+            cbct.forward(geos[0], vols[0], out=sinos[0])
+        else:
+            cbct.batch_forward(geos, vols, outs=sinos)
+
+    def adj():
+        if len(geos) == 1:
+            cbct.adjoint(geos[0], sinos[0], out=backs[0])
+        else:
+            cbct.batch_adjoint(geos, sinos, outs=backs)
+
+    for _ in range(warmup):
+        fwd()
+        adj()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        fwd()
+        ev[k][1].record()
+        adj()
+        ev[k][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tA = sum(e[0].elapsed_time(e[1]) for e in ev) / steps * 1e-3
+    tAT = sum(e[1].elapsed_time(e[2]) for e in ev) / steps * 1e-3
+    dom, tdom = ("adjoint", tAT) if tAT >= tA else ("forward", tA)
+    if len(geos) > 1:
+        dom += "_batch"
+    achieved = OPS_PER_SAMPLE * S / tdom / 1e12
+    elem = 2 if dtype == "bf16" else 4
+    return {
+        "metric": "A+A^T Gsamples/s",
+        "value": round(2 * S * steps / wall / 1e9, 3),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(wall / steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[name], "cases": len(geos),
+                   "samples_per_operator": S},
+        "kernels": {
+            "forward_ms": round(tA * 1e3, 3),
+            "adjoint_ms": round(tAT * 1e3, 3),
+            "forward_gsamples_s": round(S / tA / 1e9, 2),
+            "adjoint_gsamples_s": round(S / tAT / 1e9, 2),
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": round(achieved, 3),
+            "peak": round(VALU_PEAK_TOPS, 3),
+            "unit": "TOP/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": None,
+            "algorithmic_bytes": sum(elem * (math.prod(g.vol_shape) + math.prod(g.sino_shape))
+                                     for g in geos),
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=("c2", "c2-bf16", "c1", "c3", "c4"),
+                    help="case to time (default: the clinical-size FP32 case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recon", action="store_true",
                     help="skip the reconstruction comparison (learned net vs CGLS)")
@@ -196,6 +324,9 @@ def main():
     from paper_2512_21180_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload != "c2":
+        print(json.dumps(secondary_workload(args.workload, args.steps, args.warmup)), flush=True)
+        return
     g = W.C2
     geo = cbct.Geometry(g)
     S = geo.sample_count()

@@ -165,8 +165,9 @@ cbct_status cbct_geom_table(const cbct_geom *g, int which, void *dst, size_t cap
 /* Diagnostics: the launch plan chosen for a geometry.  Fills up to n of
  * {forward tiled (1/0), rays per thread, box in-plane, box z, tile count,
  *  adjoint bricked (1/0), window columns, window rows, LDS row stride,
- *  max row taps}.  A 0 in either flag means that operator runs the
- * one-thread-per-output kernels. */
+ *  max row taps, voxels per adjoint thread along z (bricks are 8 x 8 x 4
+ *  times that), forward tile columns (64 or 32)}.  A 0 in either flag means
+ *  that operator runs the one-thread-per-output kernels. */
 cbct_status cbct_geom_plan_info(const cbct_geom *g, int *info, int n);
 
 /* Static, human-readable description of a status code. */

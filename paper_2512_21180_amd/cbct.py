@@ -156,10 +156,11 @@ class Geometry:
         return int(s.value)
 
     def plan_info(self) -> dict:
-        v = (ctypes.c_int * 10)()
-        _check(_lib.cbct_geom_plan_info(self._h, v, 10), "cbct_geom_plan_info")
+        v = (ctypes.c_int * 12)()
+        _check(_lib.cbct_geom_plan_info(self._h, v, 12), "cbct_geom_plan_info")
         keys = ("fwd_tiled", "rays_per_thread", "box_q", "box_k", "tiles",
-                "adj_bricked", "win_cols", "win_rows", "lds_stride", "nt_max")
+                "adj_bricked", "win_cols", "win_rows", "lds_stride", "nt_max", "adj_kv",
+                "fwd_tile_cols")
         return dict(zip(keys, list(v)))
 
     def close(self):

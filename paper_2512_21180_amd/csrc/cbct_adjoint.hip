@@ -7,8 +7,9 @@
 // where p is the voxel's index along the ray's sampling axis and q_vox its
 // in-plane index; these are the weights the forward kernel applies.
 //
-// A workgroup owns a brick of 8 x 8 x 16 voxels; lane l of wave w owns the
-// voxel column (i0 + l%8, j0 + l/8) and the four voxels k0 + 4w .. k0 + 4w + 3,
+// A workgroup owns a brick of 8 x 8 x 4 KV voxels (KV = 4, 2 or 1, chosen by
+// the plan so that the window fits in LDS); lane l of wave w owns the voxel
+// column (i0 + l%8, j0 + l/8) and the KV voxels k0 + KV w .. k0 + KV w + KV - 1,
 // and keeps their sums in registers over all angles (fixed order: angles,
 // then columns, then rows), so every voxel is written once and no atomics
 // are needed.  For each angle the brick's panel window is staged in LDS,
@@ -32,16 +33,15 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kBI = 8, kBJ = 8;
-// Bricks are 8 x 8 x 16: four voxels per thread along z, one channel per
-// window element (the gather is written for C channels per element and KV
-// voxels per thread; a four-channel 8 x 8 x 4 variant measured 1.6x slower
-// per channel than this one and was dropped).
-constexpr int kKV1 = 4;
+// One channel per window element (the gather is written for C channels per
+// element; a four-channel 8 x 8 x 4 variant measured 1.6x slower per channel
+// than the single-channel 8 x 8 x 16 bricks and was dropped).
 
 struct BrickArgs {
     DevGeom g;
     int W, H, HS, NTmax;   // window columns and rows, LDS column stride (odd), taps
     int nbx, nby, nbz;
+    int KV;                // voxels per thread along z (bricks 8 x 8 x 4 KV)
 };
 
 __device__ inline float sat(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
@@ -363,7 +363,7 @@ __host__ __device__ inline int slots_per_xcd(const BrickArgs &A)
     return A.nbx * A.nbz * ((A.nby + 7) / 8);
 }
 
-template <class SS, class VS>
+template <class SS, class VS, int KV>
 __global__ void __launch_bounds__(kThreads)
 adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
               typename VS::T *__restrict__ vol)
@@ -377,7 +377,7 @@ adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
     const typename SS::T *ys[1] = {sino + ch * nsino};
     typename VS::T *vs[1] = {vol + ch * nvox};
-    gather_brick<SS, VS, 1, kKV1>(A, b, ys, vs, 1, lds);
+    gather_brick<SS, VS, 1, KV>(A, b, ys, vs, 1, lds);
 }
 
 // ---- batched adjoint: one launch over all (case, brick) items ---------------
@@ -411,15 +411,20 @@ adjoint_batch(BatchAdjArgs B)
         return;
     const typename SS::T *ys[1] = {(const typename SS::T *)C.sino};
     typename VS::T *vs[1] = {(typename VS::T *)C.vol};
-    gather_brick<SS, VS, 1, kKV1>(C.A, b, ys, vs, 1, lds);
+    switch (C.A.KV) {   // uniform over the workgroup
+    case 4: gather_brick<SS, VS, 1, 4>(C.A, b, ys, vs, 1, lds); break;
+    case 2: gather_brick<SS, VS, 1, 2>(C.A, b, ys, vs, 1, lds); break;
+    default: gather_brick<SS, VS, 1, 1>(C.A, b, ys, vs, 1, lds); break;
+    }
 }
 
 }  // namespace
 
-static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p, int bk)
+static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
 {
+    const int bk = 4 * p.KV;
     return BrickArgs{g, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI, (g.ny + kBJ - 1) / kBJ,
-                     (g.nz + bk - 1) / bk};   // WS: column stride of the window
+                     (g.nz + bk - 1) / bk, p.KV};   // WS: column stride of the window
 }
 
 static size_t brick_lds(const AdjPlan &p, int channels)
@@ -431,13 +436,20 @@ hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *
                                 cbct_dtype st, void *vol, cbct_dtype vt, int channels,
                                 hipStream_t s)
 {
-    BrickArgs A = brick_args(g, p, 4 * kKV1);
+    BrickArgs A = brick_args(g, p);
     dim3 grid(8 * slots_per_xcd(A), channels), block(kThreads);
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
-        hipLaunchKernelGGL((adjoint_brick<SS, VS>), grid, block, brick_lds(p, 1), s, A,
-                           (const typename SS::T *)sino, (typename VS::T *)vol);
+        const size_t lds = brick_lds(p, 1);
+        const auto *y = (const typename SS::T *)sino;
+        auto *x = (typename VS::T *)vol;
+        if (p.KV == 4)
+            hipLaunchKernelGGL((adjoint_brick<SS, VS, 4>), grid, block, lds, s, A, y, x);
+        else if (p.KV == 2)
+            hipLaunchKernelGGL((adjoint_brick<SS, VS, 2>), grid, block, lds, s, A, y, x);
+        else
+            hipLaunchKernelGGL((adjoint_brick<SS, VS, 1>), grid, block, lds, s, A, y, x);
         return hipGetLastError();
     });
 }
@@ -452,7 +464,7 @@ hipError_t launch_adjoint_batch(int n, const cbct_geom *const *gs, const void *c
     for (int i = 0; i < n; ++i) {
         const cbct_geom *g = gs[i];
         B.first[i] = items;
-        B.c[i] = AdjCase{brick_args(g->dev, g->adj, 4 * kKV1), sinos[i], vols[i]};
+        B.c[i] = AdjCase{brick_args(g->dev, g->adj), sinos[i], vols[i]};
         items += slots_per_xcd(B.c[i].A);
         lds = std::max(lds, brick_lds(g->adj, 1));
     }

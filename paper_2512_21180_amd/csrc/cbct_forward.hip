@@ -4,7 +4,10 @@
 // Sec. 2.2, projection operator P).  A workgroup owns one tile of up to 64
 // columns x 4R rows of one angle, all sampled along the same axis; wave w
 // holds rows [w R, w R + R) and lane l column u0 + l, so each thread carries
-// R rays of one column and shares their in-plane interpolation index.
+// R rays of one column and shares their in-plane interpolation index.  Where
+// 64 columns of rays spread over more than 64 voxels (pixels coarser than
+// voxels), tiles are 32 columns x 8R rows: lane l then holds column l % 32
+// and the rows of row group 2w + l / 32.
 //
 // The tile sweeps the voxel-centre planes of its axis.  On plane p every ray
 // of the tile lands inside a box of at most 64 (in-plane) x 32 (z) voxels
@@ -39,20 +42,23 @@ constexpr int kSlots = kMaxRows / 4;
 // [klo, klo + kw), from the corner rays' crossings widened by one voxel for
 // rounding; wave w stages rows w, w + 4, ... with lane l holding column l,
 // so each row is one load per lane.
+// tub: log2 of the tile width (6 or 5).
 template <class VS, class SS>
-__device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R,
+__device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R, int tub,
                            const typename VS::T *__restrict__ v,
                            typename SS::T *__restrict__ sino, float *lds)
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int ul = min(lane, T.nu_t - 1);
+    const int uc = lane & ((1 << tub) - 1);                   // tile column
+    const int row0 = ((w << (6 - tub)) + (lane >> tub)) * R;  // first tile row
+    const int ul = min(uc, T.nu_t - 1);
     const ColRec c = g.cols[(size_t)T.a * g.nu + T.u0 + ul];
 
     float kb[kMaxR], ks[kMaxR], acc[kMaxR];
 #pragma unroll
     for (int r = 0; r < kMaxR; ++r) {
-        const int vr = T.v0 + min(w * R + min(r, R - 1), T.nv_t - 1);
+        const int vr = T.v0 + min(row0 + min(r, R - 1), T.nv_t - 1);
         const float vz = g.rows[vr].x;
         kb[r] = fmaf(c.t0, vz, g.Kb);
         ks[r] = c.tau * vz;
@@ -149,15 +155,15 @@ __device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R,
         }
     }
 
-    if (lane < T.nu_t) {
+    if (uc < T.nu_t) {
         const float ds0 = c.dsf;
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
-            const int vr = w * R + r;
+            const int vr = row0 + r;
             if (r < R && vr < T.nv_t) {
                 const int iv = T.v0 + vr;
                 const float ds = ray_ds(ds0, c.n2, g.rows[iv].y);
-                SS::st(sino, ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + lane, acc[r] * ds);
+                SS::st(sino, ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + uc, acc[r] * ds);
             }
         }
     }
@@ -166,7 +172,7 @@ __device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R,
 struct SweepArgs {
     DevGeom g;
     const TileRec *tiles;
-    int R;
+    int R, tub;   // rays per thread, log2 of the tile width
 };
 
 template <class VS, class SS>
@@ -186,7 +192,7 @@ forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
-    sweep_tile<VS, SS>(A.g, T, A.R, vol + ch * nvox, sino + ch * nsino, lds);
+    sweep_tile<VS, SS>(A.g, T, A.R, A.tub, vol + ch * nvox, sino + ch * nsino, lds);
 }
 
 // ---- batched forward: one launch over all (case, tile) items ----------------
@@ -194,7 +200,7 @@ forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
 struct FwdCase {
     DevGeom g;
     const TileRec *tiles;
-    int R, BQ, BK, n_tiles;
+    int R, tub, n_tiles;
     const void *vol;
     void *sino;
 };
@@ -223,7 +229,8 @@ forward_batch(BatchFwdArgs B)
     const TileRec T = C.tiles[item - B.first[cs]];
     if (T.nu_t == 0)
         return;
-    sweep_tile<VS, SS>(C.g, T, C.R, (const typename VS::T *)C.vol, (typename SS::T *)C.sino, lds);
+    sweep_tile<VS, SS>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
+                       (typename SS::T *)C.sino, lds);
 }
 
 }  // namespace
@@ -232,7 +239,7 @@ hipError_t launch_forward_tiled(const DevGeom &g, const FwdPlan &p, const void *
                                 cbct_dtype vt, void *sino, cbct_dtype st, int channels,
                                 hipStream_t s)
 {
-    SweepArgs A{g, p.tiles, p.R};
+    SweepArgs A{g, p.tiles, p.R, p.TU == 32 ? 5 : 6};
     const size_t lds = 2 * (size_t)kMaxRows * kQS * sizeof(float);
     dim3 grid(p.n_tiles, channels), block(kThreads);
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
@@ -254,8 +261,8 @@ hipError_t launch_forward_batch(int n, const cbct_geom *const *gs, const void *c
     for (int i = 0; i < n; ++i) {
         const cbct_geom *g = gs[i];
         B.first[i] = items;
-        B.c[i] = FwdCase{g->dev, g->fwd.tiles, g->fwd.R, g->fwd.BQ, g->fwd.BK, g->fwd.n_tiles,
-                         vols[i], sinos[i]};
+        B.c[i] = FwdCase{g->dev, g->fwd.tiles, g->fwd.R, g->fwd.TU == 32 ? 5 : 6,
+                         g->fwd.n_tiles, vols[i], sinos[i]};
         items += g->fwd.n_tiles;
         lds = 2 * (size_t)kMaxRows * kQS * sizeof(float);
     }

@@ -60,7 +60,9 @@ static_assert(sizeof(TileRec) == 32, "TileRec layout");
 // Forward plan: LDS box per plane is BQ (in-plane) x BK (z) voxels.
 struct FwdPlan {
     bool ok = false;   // false: fall back to the one-thread-per-ray kernel
-    int R = 4;         // rays per thread along v (TV = 4 R)
+    int R = 4;         // rays per thread along v
+    int TU = 64;       // tile columns, 64 or 32 (a wave then holds two row groups);
+                       // tiles are TU x (256 / TU) R rays
     int BQ = 0, BK = 0;
     int n_tiles = 0;   // padded to a multiple of 8 (padding tiles have nu_t = 0)
     const TileRec *tiles = nullptr;   // device
@@ -88,6 +90,7 @@ struct AdjPlan {
     int W = 0, H = 0;  // footprint bounds (columns, rows)
     int WS = 0;        // LDS column stride of the window (floats, odd)
     int NTmax = 0;     // largest row-tap count
+    int KV = 4;        // voxels per thread along z: bricks are 8 x 8 x 4 KV
 };
 
 }  // namespace cbct

@@ -1,18 +1,23 @@
 // Host-side launch plans of libcbct.so, computed once per geometry in FP64.
 //
-// Forward: the panel of every angle is cut into tiles of up to 64 columns x
+// Forward: the panel of every angle is cut into tiles of up to TU columns x
 // TV rows that share a sampling axis.  A tile sweeps the voxel-centre planes
 // of that axis; on each plane every ray of the tile lands inside a box that
 // the kernel stages in LDS, at most 64 x 32 voxels.  BQ and BK are the
 // largest box extents over all tiles and planes (the extent of the box is a
 // convex function of the plane index, so its maximum is reached on the first
-// or the last plane), widened by the rounding margins the kernel relies on;
-// TV is the largest of 32, 16, 8, 4 rows whose boxes fit.
+// or the last plane), widened by the rounding margins the kernel relies on.
+// TU is 64 columns, or 32 where 64 columns of rays spread wider than 64
+// voxels (pixels coarser than the voxels); TV is the largest of 256 / TU
+// times 8, 4, 2, 1 rows whose boxes fit.
 //
-// Adjoint: the volume is cut into 8 x 8 x 16 bricks.  For every angle a
-// brick's support (voxel centres +- one pitch) projects onto the panel inside
-// a W x H window that is staged in LDS; W and H are the largest windows over
-// all bricks and angles.
+// Adjoint: the volume is cut into 8 x 8 x 4 KV bricks (KV = 4, 2 or 1 voxels
+// per thread along z).  For every angle a brick's support (voxel centres +-
+// one pitch) projects onto the panel inside a W x H window that is staged in
+// LDS; W and H are the largest windows over all bricks and angles.  The
+// tallest bricks whose window lets four workgroups share a CU's 160 KB of LDS
+// are taken, else the tallest that fit 64 KB (large voxels seen through fine
+// pixels make tall windows).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,10 +30,10 @@ namespace cbct {
 
 namespace {
 
-constexpr int kTU = 64;           // tile columns (one wavefront)
 constexpr int kMaxBoxQ = 64;      // staged box: one 64-lane row per z index
 constexpr int kMaxBoxK = 32;      // and at most 32 rows
-constexpr int kBI = 8, kBJ = 8, kBK = 16;
+constexpr int kBI = 8, kBJ = 8;
+constexpr size_t kAdjLdsShare = 40 * 1024;    // four workgroups per CU
 constexpr size_t kAdjLdsBudget = 64 * 1024;
 constexpr int kMaxTaps = 32;      // row taps per voxel and column in the adjoint
 
@@ -42,7 +47,7 @@ double row_vz(const cbct_geom_desc &d, int iv)
     return (d.off_v_mm + (iv - 0.5 * (d.nv - 1)) * d.dv_mm) / d.vz_mm;
 }
 
-TileBuild make_tiles(const cbct_geom *g, int TV)
+TileBuild make_tiles(const cbct_geom *g, int TU, int TV)
 {
     const cbct_geom_desc &d = g->desc;
     const double Kb = 0.5 * (d.nz - 1) - d.origin_mm[2] / d.vz_mm;
@@ -54,8 +59,8 @@ TileBuild make_tiles(const cbct_geom *g, int TV)
         // column ranges of one sampling axis: x planes [x_lo, x_hi), y planes elsewhere
         int ranges[3][3] = {{0, ar.x_lo, 1}, {ar.x_lo, ar.x_hi, 0}, {ar.x_hi, d.nu, 1}};
         for (auto &rg : ranges) {
-            for (int u0 = rg[0]; u0 < rg[1]; u0 += kTU) {
-                const int nu_t = std::min(kTU, rg[1] - u0);
+            for (int u0 = rg[0]; u0 < rg[1]; u0 += TU) {
+                const int nu_t = std::min(TU, rg[1] - u0);
                 const Col64 cA = col_consts64(d, c, s, u0);
                 const Col64 cB = col_consts64(d, c, s, u0 + nu_t - 1);
                 const int cls = rg[2];
@@ -187,17 +192,22 @@ void plan_host(cbct_geom *g)
 {
     const cbct_geom_desc &d = g->desc;
 
-    // ---- forward tiles: the widest tiles whose box fits 64 x 32 voxels
+    // ---- forward tiles: the largest tiles whose box fits 64 x 32 voxels
     g->fwd = FwdPlan{};
     g->tiles.clear();
     TileBuild tb;
-    int R = 0;
-    for (int r : {8, 4, 2, 1}) {
-        tb = make_tiles(g, 4 * r);
-        if (tb.BQ <= kMaxBoxQ && tb.BK <= kMaxBoxK) {
-            R = r;
-            break;
+    int R = 0, TU = 64;
+    for (int tu : {64, 32}) {
+        for (int r : {8, 4, 2, 1}) {
+            tb = make_tiles(g, tu, (256 / tu) * r);
+            if (tb.BQ <= kMaxBoxQ && tb.BK <= kMaxBoxK) {
+                R = r;
+                TU = tu;
+                break;
+            }
         }
+        if (R > 0)
+            break;
     }
     if (R > 0) {
         while (tb.tiles.size() % 8) {
@@ -209,6 +219,7 @@ void plan_host(cbct_geom *g)
         }
         g->fwd.ok = true;
         g->fwd.R = R;
+        g->fwd.TU = TU;
         g->fwd.BQ = tb.BQ;
         g->fwd.BK = tb.BK;
         g->fwd.n_tiles = (int)tb.tiles.size();
@@ -227,7 +238,15 @@ void plan_host(cbct_geom *g)
     const double t_min = (d.sid_mm - R_sup) / d.sdd_mm;
     const double rvs = d.dv_mm / d.vz_mm;
     const int NT = adj_taps_rounded((int)std::floor(2.0 / (t_min * rvs)) + 3);
-    g->adj = adjoint_plan(g, kBK, 1, NT, kAdjLdsBudget);
+    for (size_t budget : {kAdjLdsShare, kAdjLdsBudget})
+        for (int kv : {4, 2, 1}) {
+            AdjPlan p = adjoint_plan(g, 4 * kv, 1, NT, budget);
+            if (p.ok) {
+                p.KV = kv;
+                g->adj = p;
+                return;
+            }
+        }
 }
 
 }  // namespace cbct

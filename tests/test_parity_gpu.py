@@ -63,6 +63,13 @@ RAGGED = W.geometry(20, 37, 29, 3.3, 2.9, 13, 17, 11, 4.0, vy=3.5, vz=4.5, off_u
 # fine pixels overflow the adjoint window
 FINE_VOX = W.geometry(8, 48, 40, 4.0, 4.0, 40, 40, 40, 0.25)
 COARSE_VOX = W.geometry(8, 300, 200, 0.5, 0.5, 16, 16, 16, 16.0)
+# 4 and 5 mm voxels through 0.8 mm pixels: the adjoint's panel window is too
+# tall for 16-voxel bricks, the plan takes 8- and 4-voxel bricks
+SHORT_BRICKS_2 = W.geometry(10, 150, 170, 0.8, 0.8, 20, 18, 23, 4.0, off_u=20.0)
+SHORT_BRICKS_1 = W.geometry(10, 150, 170, 0.8, 0.8, 20, 18, 23, 5.0, off_u=20.0)
+# 2 mm pixels over 1 mm voxels: 64 columns of rays spread over more than 64
+# voxels, the forward takes 32-column tiles (two row groups per wave)
+NARROW_TILES = W.geometry(12, 70, 50, 2.0, 2.0, 40, 36, 30, 1.0, off_u=10.0)
 CASES = {
     "fallback_fwd": FINE_VOX,
     "fallback_adj": COARSE_VOX,
@@ -70,6 +77,9 @@ CASES = {
     "c1": W.C1,
     "c2_crop": W.cropped(W.C2, n_angles=12, nv=64),
     "c4_crop": W.cropped(W.C4, n_angles=16),
+    "short_bricks_8": SHORT_BRICKS_2,
+    "short_bricks_4": SHORT_BRICKS_1,
+    "narrow_tiles": NARROW_TILES,
 }
 
 
@@ -151,8 +161,9 @@ def test_bitwise_repeatable(dev):
 
 def test_batch_equals_single(dev):
     torch, cbct = dev
-    gs = [RAGGED, CASES["c2_crop"], W.cropped(W.C1, n_angles=7)]
-    _say("[batch] 3 cases")
+    gs = [RAGGED, CASES["c2_crop"], W.cropped(W.C1, n_angles=7), SHORT_BRICKS_1, SHORT_BRICKS_2,
+          NARROW_TILES]
+    _say("[batch] 6 cases")
     geos = [cbct.Geometry(g) for g in gs]
     xs = [torch.tensor(W.random_volume(g, i), dtype=torch.float32, device="cuda")
           for i, g in enumerate(gs)]
@@ -170,3 +181,8 @@ def test_fallback_cases_take_the_simple_kernels(dev):
     assert cbct.Geometry(COARSE_VOX).plan_info()["adj_bricked"] == 0
     assert cbct.Geometry(W.C2).plan_info()["fwd_tiled"] == 1
     assert cbct.Geometry(W.C2).plan_info()["adj_bricked"] == 1
+    assert cbct.Geometry(W.C2).plan_info()["adj_kv"] == 4
+    assert cbct.Geometry(SHORT_BRICKS_2).plan_info()["adj_kv"] == 2
+    assert cbct.Geometry(SHORT_BRICKS_1).plan_info()["adj_kv"] == 1
+    assert cbct.Geometry(W.C2).plan_info()["fwd_tile_cols"] == 64
+    assert cbct.Geometry(NARROW_TILES).plan_info()["fwd_tile_cols"] == 32

@@ -24,6 +24,11 @@ GEOMS = {
     "c4": W.C4,
     "c2": W.C2,
     "c3_8": W.c3_geometries()[8],
+    # 3 mm voxels through 0.8 mm pixels: windows too tall for 16-voxel bricks
+    "c3_10": W.c3_geometries()[10],
+    # 1.6 mm pixels over 2 mm voxels at the clinical size: 64 columns of rays
+    # spread over more than 64 voxels near 45 degrees, tiles are 32 columns
+    "c3_7": W.c3_geometries()[7],
     "steep_angles": W.geometry(7, 90, 70, 2.0, 2.0, 40, 36, 30, 3.0, off_u=60.0,
                                angles=np.array([0.1, 0.785398, 0.80, 2.3, 3.9, 5.5, 6.0])),
 }
@@ -64,8 +69,8 @@ class Host:
         names = ["Kb", "vx", "vy", "vz", "ox", "oy", "oz", "sid", "sdd", "du", "dv", "off_u",
                  "off_v", "cu", "cv", "rv0", "rvs"]
         self.s = dict(zip(names, fl[:len(names)]))
-        info = (ctypes.c_int * 10)()
-        lib.cbct_geom_plan_info(h, info, 10)
+        info = (ctypes.c_int * 12)()
+        lib.cbct_geom_plan_info(h, info, 12)
         self.info = list(info)
 
     def table(self, which, dtype):
@@ -185,13 +190,18 @@ def taps_rounded(nt):
     return 32
 
 
+def _brick_depth(h):
+    """Voxels per brick along z of the plan (4 per thread along z, KV)."""
+    return 4 * h.info[10]
+
+
 def _adj_plan(h, bk):
     """(W, H, WS, NTmax) of the plan for bricks bk voxels deep."""
-    assert bk == 16
+    assert bk == _brick_depth(h)
     return h.info[6], h.info[7], h.info[8], h.info[9]
 
 
-def _adj_brick_check(h, bx, by, bz, angles, bk=16):
+def _adj_brick_check(h, bx, by, bz, angles, bk):
     g = h.g
     s = h.s
     nx, ny, nz, nu, nv = g["nx"], g["ny"], g["nz"], g["nu"], g["nv"]
@@ -292,19 +302,19 @@ def _adj_brick_check(h, bx, by, bz, angles, bk=16):
     return checked
 
 
-@pytest.mark.parametrize("name", ["ragged", "c1", "c4", "c2", "steep_angles"])
+@pytest.mark.parametrize("name", ["ragged", "c1", "c4", "c2", "steep_angles", "c3_10"])
 def test_adjoint_windows_cover_every_weight(hosts, name):
     h = hosts[name]
     g = GEOMS[name]
     assert h.info[5] == 1, "bricked adjoint expected"
-    nbx, nby, nbz = -(-g["nx"] // 8), -(-g["ny"] // 8), -(-g["nz"] // 16)
+    nbx, nby = -(-g["nx"] // 8), -(-g["ny"] // 8)
     rng = W.rng(5)
     n_b = 3 if name in ("c2", "c4") else 6
     na = g["n_angles"]
     angs = np.unique(np.concatenate([rng.choice(na, min(na, 6), replace=False),
                                      [0, na // 8, na // 4 + 1]]))
     total = 0
-    for bk in (16,):
+    for bk in (_brick_depth(h),):
         nbz = -(-g["nz"] // bk)
         for _ in range(n_b):
             b = (int(rng.integers(nbx)), int(rng.integers(nby)), int(rng.integers(nbz)))
@@ -315,7 +325,7 @@ def test_adjoint_windows_cover_every_weight(hosts, name):
     assert total > 0
 
 
-@pytest.mark.parametrize("name", ["ragged", "c1", "c4", "c2", "steep_angles"])
+@pytest.mark.parametrize("name", ["ragged", "c1", "c4", "c2", "steep_angles", "c3_10"])
 def test_adjoint_window_bound_holds_for_every_brick(hosts, name):
     """The planned window height bounds the clipped window of every brick
     (all layers, FP32 as in the kernel) at a dozen angles: the kernel's row
@@ -325,7 +335,7 @@ def test_adjoint_window_bound_holds_for_every_brick(hosts, name):
     nx, ny, nz, nv = g["nx"], g["ny"], g["nz"], g["nv"]
     na = g["n_angles"]
     inv_dv = f32(f32(1.0) / s["dv"])
-    for bk in (16,):
+    for bk in (_brick_depth(h),):
         _, H_, _, _ = _adj_plan(h, bk)
         for a in np.linspace(0, na - 1, 12).astype(int):
             c_, s_ = h.ang_cs[a]
@@ -354,3 +364,22 @@ def test_adjoint_window_bound_holds_for_every_brick(hosts, name):
                         V1u = min(int(np.ceil(max(vv))) + 2, nv - 1)
                         if V1u >= V0:
                             assert V1u - V0 + 1 <= H_, (name, bk, a, bx, by, bz, V0, V1u, H_)
+
+
+def test_brick_depth_follows_the_window():
+    """Bricks are 16 voxels deep where the window fits four workgroups per
+    CU, shallower where large voxels meet fine pixels (all twelve mixed
+    cases stay bricked); the window always fits the 64 KB budget."""
+    for name, kv in (("c2", 4), ("c4", 4), ("c1", 4)):
+        assert Host(GEOMS[name]).info[10] == kv, name
+    for i, g in enumerate(W.c3_geometries()):
+        h = Host(g)
+        try:
+            assert h.info[5] == 1, i
+            assert h.info[10] in (1, 2, 4)
+            lds = (h.info[6] * h.info[8] + 4 * h.info[6]) * 4
+            assert lds <= 64 * 1024
+            if h.info[10] < 4:
+                assert lds <= 40 * 1024 or h.info[10] == 1
+        finally:
+            h.close()
