@@ -265,30 +265,40 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *co
             const int u = U0 + uu;
             float *dst = yt + (size_t)uu * HS * C;
             for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
-                float val[kSB][C], vsq[kSB];
+                // Raw stored values, widened at the LDS store.  Rows past V1
+                // (stored as zeros) load row V1 instead, so no load sits
+                // behind a branch that would make it wait for its value.
+                typename SS::Raw val[kSB][C];
+                float vsq[kSB];
+                bool live[kSB];
 #pragma unroll
                 for (int jj = 0; jj < kSB; ++jj) {
                     const int v = V0 + vv0 + 4 * jj;
-                    const bool live = v <= V1;   // rows V1+1 .. V0+Hs-1 are zero
-                    const size_t off = pa + (size_t)(__mul24(v, g.nu) + u);
+                    live[jj] = v <= V1;
+                    const int vr = min(v, V1);
+                    const size_t off = pa + (size_t)(__mul24(vr, g.nu) + u);
 #pragma unroll
                     for (int ch = 0; ch < C; ++ch)
-                        val[jj][ch] = (live && (C == 1 || ch < nch)) ? SS::ld(ys[ch], off) : 0.0f;
-                    vsq[jj] = live ? g.rows[v].y : 0.0f;
+                        val[jj][ch] = (C == 1 || ch < nch) ? SS::raw(ys[ch], off)
+                                                           : typename SS::Raw(0);
+                    vsq[jj] = g.rows[vr].y;
                 }
 #pragma unroll
                 for (int jj = 0; jj < kSB; ++jj) {
                     const int vv = vv0 + 4 * jj;
                     if (vv < Hs) {
                         const float ds = ray_ds(col.dsf, col.n2, vsq[jj]);
+                        float out[C];
+#pragma unroll
+                        for (int ch = 0; ch < C; ++ch)
+                            out[ch] = live[jj] ? SS::wide(val[jj][ch]) * ds : 0.0f;
                         if constexpr (C == 4) {
                             *reinterpret_cast<float4 *>(dst + (size_t)vv * 4) =
-                                make_float4(val[jj][0] * ds, val[jj][1] * ds, val[jj][2] * ds,
-                                            val[jj][3] * ds);
+                                make_float4(out[0], out[1], out[2], out[3]);
                         } else {
 #pragma unroll
                             for (int ch = 0; ch < C; ++ch)
-                                dst[(size_t)vv * C + ch] = val[jj][ch] * ds;
+                                dst[(size_t)vv * C + ch] = out[ch];
                         }
                     }
                 }

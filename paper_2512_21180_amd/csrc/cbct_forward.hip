@@ -99,24 +99,27 @@ __device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R, int tub,
         b.kw = __builtin_amdgcn_readfirstlane(b.kw);
         return b;
     };
-    auto fetch = [&](int p, const Box &b, float (&st)[kSlots]) {
+    // stored values stay raw until the LDS store, so the loads of the next
+    // plane stay in flight while this plane is summed
+    using Raw = typename VS::Raw;
+    auto fetch = [&](int p, const Box &b, Raw (&st)[kSlots]) {
         const int q = b.qlo + lane;
         const bool qin = lane < b.qw && (unsigned)q < (unsigned)nq;
         const int base = q * sq + p * sp;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-            st[s] = 0.0f;
+            st[s] = Raw(0);
             const int kk = w + 4 * s;
             const int k = b.klo + kk;
             if (kk < b.kw && qin && (unsigned)k < (unsigned)g.nz)
-                st[s] = VS::ld(v, (size_t)(base + k * sk));
+                st[s] = VS::raw(v, (size_t)(base + k * sk));
         }
     };
 
     __syncthreads();   // the previous work item's readers of lds are done
     int p = T.p_lo;
     Box nb{0, 0, 0, 0};
-    float stage[kSlots];
+    Raw stage[kSlots];
     if (p <= T.p_hi) {
         nb = box_of(p);
         fetch(p, nb, stage);
@@ -127,7 +130,7 @@ __device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R, int tub,
 #pragma unroll
         for (int s = 0; s < kSlots; ++s)
             if (w + 4 * s < cb.kw)
-                buf[(w + 4 * s) * kQS + lane] = stage[s];
+                buf[(w + 4 * s) * kQS + lane] = VS::wide(stage[s]);
         __syncthreads();
         if (p < T.p_hi) {
             nb = box_of(p + 1);

@@ -1,5 +1,9 @@
 // Storage conversions for the projector kernels: FP32 arithmetic on FP32,
 // BF16 or FP16 buffers (widened on load, rounded to nearest-even on store).
+// `raw` loads the stored bits into a 32-bit register and `wide` widens them:
+// a kernel that keeps loads in flight across other work holds raw values and
+// widens them where they are used (widening, or packing two 16-bit values
+// into one register, right after the load would wait for it).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,15 +15,18 @@ namespace cbct {
 struct F32 {
     using T = float;
     __device__ static float ld(const T *p, size_t i) { return p[i]; }
+    using Raw = float;
+    __device__ static Raw raw(const T *p, size_t i) { return p[i]; }
+    __device__ static float wide(Raw x) { return x; }
     __device__ static void st(T *p, size_t i, float v) { p[i] = v; }
 };
 
 struct BF16 {
     using T = uint16_t;
-    __device__ static float ld(const T *p, size_t i)
-    {
-        return __uint_as_float(((uint32_t)p[i]) << 16);
-    }
+    using Raw = uint32_t;
+    __device__ static float ld(const T *p, size_t i) { return wide(p[i]); }
+    __device__ static Raw raw(const T *p, size_t i) { return p[i]; }
+    __device__ static float wide(Raw x) { return __uint_as_float(x << 16); }
     __device__ static void st(T *p, size_t i, float v)
     {
         uint32_t b = __float_as_uint(v);
@@ -35,6 +42,15 @@ struct BF16 {
 struct F16 {
     using T = _Float16;
     __device__ static float ld(const T *p, size_t i) { return (float)p[i]; }
+    using Raw = uint32_t;
+    __device__ static Raw raw(const T *p, size_t i)
+    {
+        return __builtin_bit_cast(uint16_t, p[i]);
+    }
+    __device__ static float wide(Raw x)
+    {
+        return (float)__builtin_bit_cast(_Float16, (uint16_t)x);
+    }
     __device__ static void st(T *p, size_t i, float v) { p[i] = (_Float16)v; }
 };
 
