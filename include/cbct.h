@@ -159,7 +159,10 @@ cbct_status cbct_geom_create_host(const cbct_geom_desc *desc, cbct_geom **out);
  * (float32 x 2); 3 forward tiles {angle, axis, u0, n_u, v0, n_v, p_lo, p_hi}
  * (int32 x 8); 4 the scalar block {n_angles, nu, nv, nx, ny, nz (int32), Kb,
  * vx, vy, vz, ox, oy, oz, sid, sdd, du, dv, off_u, off_v, cu, cv, rv0, rvs
- * (float32)}. */
+ * (float32)}; 5 adjoint panel windows per angle and 8 x 8 brick column
+ * ([n_angles][ceil(ny/8)][ceil(nx/8)], empty when the adjoint runs the
+ * one-thread-per-voxel kernel) {lambda_min, lambda_max (float32), u0 | u1 << 16,
+ * row taps (int32)}. */
 cbct_status cbct_geom_table(const cbct_geom *g, int which, void *dst, size_t cap, size_t *bytes);
 
 /* Diagnostics: the launch plan chosen for a geometry.  Fills up to n of

@@ -39,6 +39,7 @@ constexpr int kBI = 8, kBJ = 8;
 
 struct BrickArgs {
     DevGeom g;
+    const BrickWin *wins;  // [n_angles][nby][nbx] panel windows
     int W, H, HS, NTmax;   // window columns and rows, LDS column stride (odd), taps
     int nbx, nby, nbz;
     int KV;                // voxels per thread along z (bricks 8 x 8 x 4 KV)
@@ -195,18 +196,15 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *co
     const float cxv = g.ox + ((float)ic - 0.5f * (float)(g.nx - 1)) * g.vx;
     const float cyv = g.oy + ((float)jc - 0.5f * (float)(g.ny - 1)) * g.vy;
 
-    // brick support box (voxel centres +- one pitch), uniform
-    const int i0 = bx * kBI, i1 = min(i0 + kBI, g.nx) - 1;
-    const int j0 = by * kBJ, j1 = min(j0 + kBJ, g.ny) - 1;
+    // z extent of the brick's support (voxel centres +- one pitch), uniform
     const int kz0 = bz * kBK, kz1 = min(kz0 + kBK, g.nz) - 1;
-    const float xs0 = g.ox + ((float)i0 - 0.5f * (float)(g.nx - 1)) * g.vx - g.vx;
-    const float xs1 = g.ox + ((float)i1 - 0.5f * (float)(g.nx - 1)) * g.vx + g.vx;
-    const float ys0 = g.oy + ((float)j0 - 0.5f * (float)(g.ny - 1)) * g.vy - g.vy;
-    const float ys1 = g.oy + ((float)j1 - 0.5f * (float)(g.ny - 1)) * g.vy + g.vy;
     const float zs0 = g.oz + ((float)kz0 - 0.5f * (float)(g.nz - 1)) * g.vz - g.vz;
     const float zs1 = g.oz + ((float)kz1 - 0.5f * (float)(g.nz - 1)) * g.vz + g.vz;
+    // the brick column's panel windows, one per angle (host FP64)
+    const BrickWin *wcol = A.wins + (size_t)by * A.nbx + bx;
+    const size_t wstep = (size_t)A.nbx * A.nby;
 
-    const float inv_du = 1.0f / g.du, inv_dv = 1.0f / g.dv, inv_sdd = 1.0f / g.sdd;
+    const float inv_du = 1.0f / g.du, inv_dv = 1.0f / g.dv;
     // z of this wave's first voxel layer (wave-uniform)
     const float zc_w0 = g.oz + ((float)k0 - 0.5f * (float)(g.nz - 1)) * g.vz;
     const float inv_rvs = 1.0f / g.rvs;
@@ -219,33 +217,23 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *co
 
     __syncthreads();   // the previous work item's readers of lds are done
     for (int a = 0; a < g.n_angles; ++a) {
-        const AngRec ar = g.angs[a];
-        // ---- panel window of the brick (uniform)
-        float umin = 1e30f, umax = -1e30f, vmin = 1e30f, vmax = -1e30f, tmin = 1e30f;
-        float lmin = 1e30f, lmax = -1e30f;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float x = (q & 1) ? xs1 : xs0, yy = (q & 2) ? ys1 : ys0;
-            float u, lam;
-            project_xy(g, inv_du, ar.c, ar.s, x, yy, u, lam);
-            umin = fminf(umin, u);
-            umax = fmaxf(umax, u);
-            lmin = fminf(lmin, lam);
-            lmax = fmaxf(lmax, lam);
-            const float va = fmaf(fmaf(lam, zs0, -g.off_v), inv_dv, g.cv);
-            const float vb = fmaf(fmaf(lam, zs1, -g.off_v), inv_dv, g.cv);
-            vmin = fminf(vmin, fminf(va, vb));
-            vmax = fmaxf(vmax, fmaxf(va, vb));
-            tmin = fminf(tmin, (g.sid - fmaf(ar.c, x, ar.s * yy)) * inv_sdd);
-        }
-        const int U0 = max((int)floorf(umin) - 1, 0);
-        const int U1 = min(min((int)ceilf(umax) + 1, g.nu - 1), U0 + A.W - 1);
-        int NT = adj_taps_rounded(min((int)floorf(2.0f / (tmin * g.rvs)) + 3, A.NTmax));
-        NT = __builtin_amdgcn_readfirstlane(NT);
+        // ---- panel window of the brick (uniform): columns and row taps from
+        // the table, rows from the extreme source-panel scales (positive) at
+        // the support's lowest and highest z
+        const BrickWin bw = wcol[(size_t)a * wstep];
+        const int U0 = bw.u01 & 0xffff;
+        const int U1 = min(bw.u01 >> 16, U0 + A.W - 1);
+        if (U0 > U1)
+            continue;
+        const float lmin = bw.lmin, lmax = bw.lmax;
+        const float vmin = fmaf(fminf(lmin * zs0, lmax * zs0) - g.off_v, inv_dv, g.cv);
+        const float vmax = fmaf(fmaxf(lmin * zs1, lmax * zs1) - g.off_v, inv_dv, g.cv);
         const int V0 = max((int)floorf(vmin) - 2, 0);
         const int V1 = min(min((int)ceilf(vmax) + 2, g.nv - 1), V0 + A.H - 1);
-        if (U0 > U1 || V0 > V1)
+        if (V0 > V1)
             continue;
+        const int NT = bw.nt;
+        const AngRec ar = g.angs[a];
         const int Wc = U1 - U0 + 1;
         // staged rows; rows past V1 (only when the window is shorter than a
         // run) are zero
@@ -433,8 +421,8 @@ adjoint_batch(BatchAdjArgs B)
 static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
 {
     const int bk = 4 * p.KV;
-    return BrickArgs{g, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI, (g.ny + kBJ - 1) / kBJ,
-                     (g.nz + bk - 1) / bk, p.KV};   // WS: column stride of the window
+    return BrickArgs{g, p.wins, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI,
+                     (g.ny + kBJ - 1) / kBJ, (g.nz + bk - 1) / bk, p.KV};   // WS: column stride
 }
 
 static size_t brick_lds(const AdjPlan &p, int channels)

@@ -271,7 +271,8 @@ static hipError_t device_upload(cbct_geom *g)
     size_t nang = g->angs.size() * sizeof(AngRec);
     size_t nrow = g->rows.size() * sizeof(float2);
     size_t ntile = g->tiles.size() * sizeof(TileRec);
-    size_t total = up(ncol) + up(nang) + up(nrow) + up(ntile);
+    size_t nwin = g->wins.size() * sizeof(BrickWin);
+    size_t total = up(ncol) + up(nang) + up(nrow) + up(ntile) + up(nwin);
     hipError_t e = hipGetDevice(&g->device);
     if (e == hipSuccess)
         e = hipMalloc(&g->dev_block, total);
@@ -279,6 +280,7 @@ static hipError_t device_upload(cbct_geom *g)
         return e;
     char *base = (char *)g->dev_block;
     char *pc = base, *pa = pc + up(ncol), *pr = pa + up(nang), *pt = pr + up(nrow);
+    char *pw = pt + up(ntile);
     e = hipMemcpy(pc, g->cols.data(), ncol, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(pa, g->angs.data(), nang, hipMemcpyHostToDevice);
@@ -286,10 +288,13 @@ static hipError_t device_upload(cbct_geom *g)
         e = hipMemcpy(pr, g->rows.data(), nrow, hipMemcpyHostToDevice);
     if (e == hipSuccess && ntile)
         e = hipMemcpy(pt, g->tiles.data(), ntile, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nwin)
+        e = hipMemcpy(pw, g->wins.data(), nwin, hipMemcpyHostToDevice);
     g->dev.cols = (const ColRec *)pc;
     g->dev.angs = (const AngRec *)pa;
     g->dev.rows = (const float2 *)pr;
     g->fwd.tiles = ntile ? (const TileRec *)pt : nullptr;
+    g->adj.wins = nwin ? (const BrickWin *)pw : nullptr;
     return e;
 }
 
@@ -327,6 +332,7 @@ extern "C" cbct_status cbct_geom_table(const cbct_geom *g, int which, void *dst,
     case 2: src = g->rows.data(); n = g->rows.size() * sizeof(float2); break;
     case 3: src = g->tiles.data(); n = g->tiles.size() * sizeof(TileRec); break;
     case 4: src = &g->dev; n = offsetof(DevGeom, cols); break;
+    case 5: src = g->wins.data(); n = g->wins.size() * sizeof(BrickWin); break;
     default: return CBCT_E_ARG;
     }
     *bytes = n;

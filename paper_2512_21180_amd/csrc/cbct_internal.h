@@ -85,12 +85,25 @@ __host__ __device__ inline int adj_taps_rounded(int nt)
 
 // Adjoint plan: bricks of 8 x 8 x 16 voxels; per angle the brick's panel
 // footprint (at most W x H pixels, clipped to the panel) is staged in LDS.
+// Panel window of one adjoint brick column (8 x 8 voxels, all z) at one
+// angle, from the FP64 projections of its support box (voxel centres +- one
+// pitch): columns [u0, u1] (u0 > u1: the column is not seen), the extreme
+// source-panel scales (a point at height z lands at V = lambda z) and the
+// row taps per voxel and column its rays need.
+struct BrickWin {
+    float lmin, lmax;
+    int u01;           // u0 | u1 << 16
+    int nt;
+};
+static_assert(sizeof(BrickWin) == 16, "BrickWin layout");
+
 struct AdjPlan {
     bool ok = false;   // false: fall back to the one-thread-per-voxel kernel
     int W = 0, H = 0;  // footprint bounds (columns, rows)
     int WS = 0;        // LDS column stride of the window (floats, odd)
     int NTmax = 0;     // largest row-tap count
     int KV = 4;        // voxels per thread along z: bricks are 8 x 8 x 4 KV
+    const BrickWin *wins = nullptr;   // device: [n_angles][nby][nbx]
 };
 
 }  // namespace cbct
@@ -107,6 +120,7 @@ struct cbct_geom {
     std::vector<cbct::AngRec> angs;
     std::vector<float2> rows;
     std::vector<cbct::TileRec> tiles;
+    std::vector<cbct::BrickWin> wins;   // adjoint brick-column windows
     cbct::FwdPlan fwd;               // fwd.tiles points into dev_block
     cbct::AdjPlan adj;
 };

@@ -16,8 +16,9 @@
 // one pitch) projects onto the panel inside a W x H window that is staged in
 // LDS; W and H are the largest windows over all bricks and angles.  The
 // tallest bricks whose window lets four workgroups share a CU's 160 KB of LDS
-// are taken, else the tallest that fit 64 KB (large voxels seen through fine
-// pixels make tall windows).
+// and that still give two bricks per CU are taken (small volumes take
+// shorter bricks to fill the chip), else the tallest that fit 64 KB (large
+// voxels seen through fine pixels make tall windows).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,6 +36,7 @@ constexpr int kMaxBoxK = 32;      // and at most 32 rows
 constexpr int kBI = 8, kBJ = 8;
 constexpr size_t kAdjLdsShare = 40 * 1024;    // four workgroups per CU
 constexpr size_t kAdjLdsBudget = 64 * 1024;
+constexpr long kMinBricks = 2 * 256;          // two bricks per CU
 constexpr int kMaxTaps = 32;      // row taps per voxel and column in the adjoint
 
 struct TileBuild {
@@ -114,23 +116,31 @@ TileBuild make_tiles(const cbct_geom *g, int TU, int TV)
     return tb;
 }
 
-// Window bounds of bricks 8 x 8 x bk staging `channels` channels per
-// element; ok when the window fits the LDS budget.  Every brick and angle
-// is evaluated: per (angle, brick column) the corner projections give the
-// column range and the extreme source-panel scales, and per brick layer the
-// row range follows from them (rows are linear in z for a fixed scale).
-// Both ranges are clipped to the panel as the kernel clips them, with the
-// kernel's margins plus one for FP32 rounding on each side.
-AdjPlan adjoint_plan(const cbct_geom *g, int bk, int channels, int NT, size_t budget)
+// Panel windows of every brick column (8 x 8 voxels, all z) at every angle,
+// in FP64: the projections of the support box corners (voxel centres +- one
+// pitch) give the column range (one column of margin on each side, clipped
+// to the panel), the extreme source-panel scales and the smallest ray
+// parameter t, from which the row taps follow (a voxel's non-zero rows in
+// one column span less than 2 / (t dv / vz) rows, plus three for the run
+// start's rounding).  The kernel reads these instead of computing them.
+struct WinTable {
+    std::vector<BrickWin> w;         // [n_angles][nby][nbx]
+    std::vector<double> lmin, lmax;  // the scales in FP64
+    int W = 0;                       // widest column range
+};
+
+WinTable brick_windows(const cbct_geom *g, int NTmax)
 {
     const cbct_geom_desc &d = g->desc;
-    AdjPlan p{};
-    int W = 0, H = 0;
     const int nbx = (d.nx + kBI - 1) / kBI, nby = (d.ny + kBJ - 1) / kBJ;
-    const int nbz = (d.nz + bk - 1) / bk;
+    const size_t n = (size_t)d.n_angles * nby * nbx;
+    WinTable t;
+    t.w.resize(n);
+    t.lmin.resize(n);
+    t.lmax.resize(n);
+    const double rvs = d.dv_mm / d.vz_mm;
     auto cx = [&](double i) { return d.origin_mm[0] + (i - 0.5 * (d.nx - 1)) * d.vx_mm; };
     auto cy = [&](double j) { return d.origin_mm[1] + (j - 0.5 * (d.ny - 1)) * d.vy_mm; };
-    auto cz = [&](double k) { return d.origin_mm[2] + (k - 0.5 * (d.nz - 1)) * d.vz_mm; };
     for (int a = 0; a < d.n_angles; ++a) {
         const double c = std::cos(g->angles[a]), s = std::sin(g->angles[a]);
         for (int by = 0; by < nby; ++by)
@@ -139,36 +149,71 @@ AdjPlan adjoint_plan(const cbct_geom *g, int bk, int channels, int NT, size_t bu
                 const int j0 = by * kBJ, j1 = std::min(j0 + kBJ, d.ny) - 1;
                 const double xs[2] = {cx(i0) - d.vx_mm, cx(i1) + d.vx_mm};
                 const double ys[2] = {cy(j0) - d.vy_mm, cy(j1) + d.vy_mm};
-                double umin = 1e300, umax = -1e300, lmin = 1e300, lmax = -1e300;
+                double umin = 1e300, umax = -1e300, lmin = 1e300, lmax = -1e300, tmin = 1e300;
                 for (double x : xs)
                     for (double y : ys) {
-                        const double lam = -d.sdd_mm / (c * x + s * y - d.sid_mm);
+                        const double den = c * x + s * y - d.sid_mm;
+                        const double lam = -d.sdd_mm / den;
                         const double u =
                             (lam * (-s * x + c * y) - d.off_u_mm) / d.du_mm + 0.5 * (d.nu - 1);
                         umin = std::min(umin, u);
                         umax = std::max(umax, u);
                         lmin = std::min(lmin, lam);
                         lmax = std::max(lmax, lam);
+                        tmin = std::min(tmin, -den / d.sdd_mm);
                     }
-                const double u0 = std::max(std::floor(umin) - 2.0, 0.0);
-                const double u1 = std::min(std::ceil(umax) + 2.0, (double)(d.nu - 1));
-                if (u1 < u0)
-                    continue;
-                W = std::max(W, (int)(u1 - u0) + 1);
-                for (int bz = 0; bz < nbz; ++bz) {
-                    const int k0 = bz * bk, k1 = std::min(k0 + bk, d.nz) - 1;
-                    const double zl = cz(k0) - d.vz_mm, zh = cz(k1) + d.vz_mm;
-                    const double vmin =
-                        (std::min(lmin * zl, lmax * zl) - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
-                    const double vmax =
-                        (std::max(lmin * zh, lmax * zh) - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
-                    const double v0 = std::max(std::floor(vmin) - 3.0, 0.0);
-                    const double v1 = std::min(std::ceil(vmax) + 3.0, (double)(d.nv - 1));
-                    if (v1 >= v0)
-                        H = std::max(H, (int)(v1 - v0) + 1);
+                const int u0 = (int)std::max(std::floor(umin) - 1.0, 0.0);
+                const int u1 = (int)std::min(std::ceil(umax) + 1.0, (double)(d.nu - 1));
+                const size_t e = ((size_t)a * nby + by) * nbx + bx;
+                BrickWin &bw = t.w[e];
+                bw.lmin = (float)lmin;
+                bw.lmax = (float)lmax;
+                if (u0 <= u1) {
+                    bw.u01 = u0 | (u1 << 16);
+                    t.W = std::max(t.W, u1 - u0 + 1);
+                } else {
+                    bw.u01 = 1;   // u0 = 1 > u1 = 0: not seen
                 }
+                const int nt = (int)std::floor(2.0 / (tmin * rvs)) + 3;
+                bw.nt = adj_taps_rounded(std::min(nt, NTmax));
+                t.lmin[e] = lmin;
+                t.lmax[e] = lmax;
             }
     }
+    return t;
+}
+
+// Window bounds of bricks 8 x 8 x bk staging `channels` channels per
+// element; ok when the window fits the LDS budget.  Per brick layer the row
+// range follows from the brick column's scales (rows are linear in z for a
+// fixed scale), clipped to the panel as the kernel clips it, with the
+// kernel's margins plus one for its FP32 rounding on each side.
+AdjPlan adjoint_plan(const cbct_geom *g, const WinTable &t, int bk, int channels, int NT,
+                     size_t budget)
+{
+    const cbct_geom_desc &d = g->desc;
+    AdjPlan p{};
+    int H = 0;
+    const int nbz = (d.nz + bk - 1) / bk;
+    auto cz = [&](double k) { return d.origin_mm[2] + (k - 0.5 * (d.nz - 1)) * d.vz_mm; };
+    for (size_t e = 0; e < t.w.size(); ++e) {
+        if ((t.w[e].u01 & 0xffff) > (t.w[e].u01 >> 16))
+            continue;
+        const double lmin = t.lmin[e], lmax = t.lmax[e];
+        for (int bz = 0; bz < nbz; ++bz) {
+            const int k0 = bz * bk, k1 = std::min(k0 + bk, d.nz) - 1;
+            const double zl = cz(k0) - d.vz_mm, zh = cz(k1) + d.vz_mm;
+            const double vmin =
+                (std::min(lmin * zl, lmax * zl) - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
+            const double vmax =
+                (std::max(lmin * zh, lmax * zh) - d.off_v_mm) / d.dv_mm + 0.5 * (d.nv - 1);
+            const double v0 = std::max(std::floor(vmin) - 3.0, 0.0);
+            const double v1 = std::min(std::ceil(vmax) + 3.0, (double)(d.nv - 1));
+            if (v1 >= v0)
+                H = std::max(H, (int)(v1 - v0) + 1);
+        }
+    }
+    const int W = t.W;
     // a tap run never leaves the window (its start is clamped), so the
     // window needs the brick's rows, or one run when that is taller
     H = std::max(H, NT);
@@ -238,15 +283,28 @@ void plan_host(cbct_geom *g)
     const double t_min = (d.sid_mm - R_sup) / d.sdd_mm;
     const double rvs = d.dv_mm / d.vz_mm;
     const int NT = adj_taps_rounded((int)std::floor(2.0 / (t_min * rvs)) + 3);
-    for (size_t budget : {kAdjLdsShare, kAdjLdsBudget})
+    const long bricks_xy = (long)((d.nx + kBI - 1) / kBI) * ((d.ny + kBJ - 1) / kBJ);
+    WinTable wt = brick_windows(g, NT);
+    g->wins = wt.w;
+    for (size_t budget : {kAdjLdsShare, kAdjLdsBudget}) {
+        AdjPlan shortest{};
         for (int kv : {4, 2, 1}) {
-            AdjPlan p = adjoint_plan(g, 4 * kv, 1, NT, budget);
-            if (p.ok) {
-                p.KV = kv;
+            AdjPlan p = adjoint_plan(g, wt, 4 * kv, 1, NT, budget);
+            if (!p.ok)
+                continue;
+            p.KV = kv;
+            shortest = p;
+            if (bricks_xy * ((d.nz + 4 * kv - 1) / (4 * kv)) >= kMinBricks) {
                 g->adj = p;
                 return;
             }
         }
+        if (shortest.ok) {   // no height gives kMinBricks: the shortest bricks
+            g->adj = shortest;
+            return;
+        }
+    }
+    g->wins.clear();   // the one-thread-per-voxel kernel needs no windows
 }
 
 }  // namespace cbct

@@ -64,7 +64,8 @@ RAGGED = W.geometry(20, 37, 29, 3.3, 2.9, 13, 17, 11, 4.0, vy=3.5, vz=4.5, off_u
 FINE_VOX = W.geometry(8, 48, 40, 4.0, 4.0, 40, 40, 40, 0.25)
 COARSE_VOX = W.geometry(8, 300, 200, 0.5, 0.5, 16, 16, 16, 16.0)
 # 4 and 5 mm voxels through 0.8 mm pixels: the adjoint's panel window is too
-# tall for 16-voxel bricks, the plan takes 8- and 4-voxel bricks
+# tall for 16-voxel bricks (and the volumes too small for two bricks per CU),
+# the plan takes 4-voxel bricks; 64^3 (c1) takes 8-voxel bricks (512 of them)
 SHORT_BRICKS_2 = W.geometry(10, 150, 170, 0.8, 0.8, 20, 18, 23, 4.0, off_u=20.0)
 SHORT_BRICKS_1 = W.geometry(10, 150, 170, 0.8, 0.8, 20, 18, 23, 5.0, off_u=20.0)
 # 2 mm pixels over 1 mm voxels: 64 columns of rays spread over more than 64
@@ -182,7 +183,8 @@ def test_fallback_cases_take_the_simple_kernels(dev):
     assert cbct.Geometry(W.C2).plan_info()["fwd_tiled"] == 1
     assert cbct.Geometry(W.C2).plan_info()["adj_bricked"] == 1
     assert cbct.Geometry(W.C2).plan_info()["adj_kv"] == 4
-    assert cbct.Geometry(SHORT_BRICKS_2).plan_info()["adj_kv"] == 2
+    assert cbct.Geometry(W.C1).plan_info()["adj_kv"] == 2
+    assert cbct.Geometry(SHORT_BRICKS_2).plan_info()["adj_kv"] == 1
     assert cbct.Geometry(SHORT_BRICKS_1).plan_info()["adj_kv"] == 1
     assert cbct.Geometry(W.C2).plan_info()["fwd_tile_cols"] == 64
     assert cbct.Geometry(NARROW_TILES).plan_info()["fwd_tile_cols"] == 32
