@@ -14,12 +14,17 @@
 // then columns, then rows), so every voxel is written once and no atomics
 // are needed.  For each angle the brick's panel window is staged in LDS,
 // pre-multiplied by the ray length per plane ds, together with the column
-// constants.  Per voxel and column, the rows with non-zero weight form a run
-// that starts below the row where the ray crosses z = k - 1 and holds at
-// most NT rows; the taps use the clamped hat, so rows outside the run add
-// exact zeros (a run that would leave the window starts lower instead).
-// The window is stored column-major, so a run is consecutive LDS words read
-// two at a time with immediate offsets in a fully unrolled sequence.
+// constants.  Per voxel and column, the rows with non-zero weight lie above
+// the row v_c where the ray crosses z = k - 1 and span less than 2 / beta
+// rows (beta: rows to z index, at least that of the brick's nearest point
+// to the source); the run of NT = floor(2 / beta) + 2 rows that starts at
+// floor(v_c + 1/64) holds them all (the 1/64 row exceeds the rounding of
+// v_c many times, so the start is floor(v_c) or, when v_c lies within 1/64
+// below an integer, that integer, and every row below it has zero weight).
+// The taps use the clamped hat, so rows outside the support add exact
+// zeros (a run that would leave the window starts lower instead).  The
+// window is stored column-major, so a run is consecutive LDS words read two
+// at a time with immediate offsets in a fully unrolled sequence.
 
 #include <hip/hip_runtime.h>
 
@@ -75,8 +80,10 @@ struct GatherIn {
 // Accumulate one angle's contributions into acc, reading NT taps per voxel
 // and column (rows past the non-zero run have zero weight).  The window holds
 // C channels per element; KV voxels per thread along z.
+// Both gather functions are forced inline: a call would impose the calling
+// convention's register budget and stack on the kernel.
 template <int NT, int C, int KV>
-__device__ inline void gather_angle(const GatherIn &in, float (&acc)[KV][C])
+__device__ __forceinline__ void gather_angle(const GatherIn &in, float (&acc)[KV][C])
 {
     const DevGeom &g = in.g;
     const AngRec &ar = in.ar;
@@ -133,16 +140,16 @@ for (int cls = 0; cls < 2; ++cls) {
             const float t = fmaf(fp, cq.w, cq.z);
             const float beta = t * g.rvs;
             const float rt = __builtin_amdgcn_rcpf(t);
-            // row where the ray crosses z index kk - 1: vA + kk vB
+            // row where the ray crosses z index kk - 1, plus 1/64: vA + kk vB
             const float vB = rt * inv_rvs;
-            const float vA = fmaf(fmaf(-1.0f - g.Kb, rt, -g.rv0), inv_rvs, g.cv);
+            const float vA = fmaf(fmaf(-1.0f - g.Kb, rt, -g.rv0), inv_rvs, g.cv + 0.015625f);
             const float *ycol = yt + ((u - U0) * HS - V0) * C;
 #pragma unroll
             for (int n = 0; n < KV; ++n) {
                 const float kk = (float)(k0 + n);
-                // one row below that crossing, for rounding; a start moved
-                // down to VS1 only adds rows below the run (zero weight)
-                const int vs = min(max((int)floorf(fmaf(kk, vB, vA)) - 1, V0), VS1);
+                // a start moved down to VS1 only adds rows below the run
+                // (zero weight)
+                const int vs = min(max((int)floorf(fmaf(kk, vB, vA)), V0), VS1);
                 float s = fmaf(t, fmaf((float)vs - g.cv, g.rvs, g.rv0), g.Kb - kk);
                 const float *py = ycol + vs * C;
                 float csum[C];
@@ -176,8 +183,10 @@ for (int cls = 0; cls < 2; ++cls) {
 // column-major with C channels per element ([W][HS][C], HS odd so that a row
 // of lanes writes distinct banks), and the column table.
 template <class SS, class VS, int C, int KV>
-__device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *const (&ys)[C],
-                             typename VS::T *const (&vols)[C], int nch, float *lds)
+__device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
+                                             const typename SS::T *const (&ys)[C],
+                                             typename VS::T *const (&vols)[C], int nch,
+                                             float *lds)
 {
     constexpr int kBK = 4 * KV;
     constexpr int kSB = C == 1 ? 8 : 4;   // rows per staging batch (loads in flight)
@@ -307,19 +316,27 @@ __device__ void gather_brick(const BrickArgs &A, int b, const typename SS::T *co
                 continue;
         }
         // ---- gather with a compile-time tap count (NT rounded up to a
-        // supported even count; extra taps read zero weight)
+        // supported count; extra taps read zero weight)
         const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, V1, VS1, ic, jc, k0, cxv, cyv, inv_du,
                           inv_rvs};
         switch (NT) {
         case 4: gather_angle<4, C, KV>(in, acc); break;
+        case 5: gather_angle<5, C, KV>(in, acc); break;
         case 6: gather_angle<6, C, KV>(in, acc); break;
+        case 7: gather_angle<7, C, KV>(in, acc); break;
         case 8: gather_angle<8, C, KV>(in, acc); break;
+        case 9: gather_angle<9, C, KV>(in, acc); break;
         case 10: gather_angle<10, C, KV>(in, acc); break;
+        case 11: gather_angle<11, C, KV>(in, acc); break;
         case 12: gather_angle<12, C, KV>(in, acc); break;
+        case 13: gather_angle<13, C, KV>(in, acc); break;
         case 14: gather_angle<14, C, KV>(in, acc); break;
+        case 15: gather_angle<15, C, KV>(in, acc); break;
         case 16: gather_angle<16, C, KV>(in, acc); break;
+        case 18: gather_angle<18, C, KV>(in, acc); break;
         case 20: gather_angle<20, C, KV>(in, acc); break;
         case 24: gather_angle<24, C, KV>(in, acc); break;
+        case 28: gather_angle<28, C, KV>(in, acc); break;
         default: gather_angle<32, C, KV>(in, acc); break;
         }
     }

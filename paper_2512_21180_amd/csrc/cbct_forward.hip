@@ -44,7 +44,7 @@ constexpr int kSlots = kMaxRows / 4;
 // so each row is one load per lane.
 // tub: log2 of the tile width (6 or 5).
 template <class VS, class SS>
-__device__ void sweep_tile(const DevGeom &g, const TileRec &T, int R, int tub,
+__device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, int R, int tub,
                            const typename VS::T *__restrict__ v,
                            typename SS::T *__restrict__ sino, float *lds)
 {

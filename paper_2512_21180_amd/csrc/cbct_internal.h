@@ -69,17 +69,21 @@ struct FwdPlan {
 };
 
 // Row taps the adjoint reads per voxel and column: the needed count rounded
-// up to a count its kernel is instantiated for (4..16 even, 20, 24, 32).
+// up to a count its kernel is instantiated for (4..16, 18, 20, 24, 28, 32).
 __host__ __device__ inline int adj_taps_rounded(int nt)
 {
     if (nt <= 4)
         return 4;
     if (nt <= 16)
-        return nt + (nt & 1);
+        return nt;
+    if (nt <= 18)
+        return 18;
     if (nt <= 20)
         return 20;
     if (nt <= 24)
         return 24;
+    if (nt <= 28)
+        return 28;
     return 32;
 }
 

@@ -190,7 +190,7 @@ def test_forward_box_indices_stay_in_lds(hosts, name):
 
 def taps_rounded(nt):
     """Tap counts the adjoint kernel is instantiated for."""
-    for c in (4, 6, 8, 10, 12, 14, 16, 20, 24):
+    for c in (4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 18, 20, 24, 28):
         if nt <= c:
             return c
     return 32
@@ -293,9 +293,10 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
                             rows_sup = np.nonzero(np.abs(kf.astype(np.float64) - kk) < 1.0)[0]
                             inv_rvs = f32(f32(1.0) / rvs)
                             vB = f32(rt * inv_rvs)
-                            vA = fma32(fma32(f32(-1.0) - Kb, rt, -rv0), inv_rvs, cv)
+                            vA = fma32(fma32(f32(-1.0) - Kb, rt, -rv0), inv_rvs,
+                                       f32(cv + f32(0.015625)))
                             vf = fma32(f32(kk), vB, vA)
-                            vstart = min(max(int(np.floor(vf)) - 1, V0), VS1)
+                            vstart = min(max(int(np.floor(vf)), V0), VS1)
                             assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)
                                           & (rows_sup <= V1)), \
                                 (a, i, j, kk, u, rows_sup, vstart, NT, V1)
