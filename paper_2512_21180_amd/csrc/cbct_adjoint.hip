@@ -92,7 +92,19 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&acc)[KV
     const float cxv = in.cxv, cyv = in.cyv, inv_du = in.inv_du, inv_rvs = in.inv_rvs;
     const float *yt = in.yt;
     const float4 *cr = in.cr;
-for (int cls = 0; cls < 2; ++cls) {
+    // Per voxel kk: the row where a ray with parameter t crosses z index
+    // kk - 1, plus 1/64, is Bk / t + A0; the hat argument at row r is
+    // t ((r - cv) rvs + rv0) + Kb - kk.
+    float Bk[KV], KbK[KV];
+#pragma unroll
+    for (int n = 0; n < KV; ++n) {
+        const float kk = (float)(k0 + n);
+        Bk[n] = (kk - 1.0f - g.Kb) * inv_rvs;
+        KbK[n] = g.Kb - kk;
+    }
+    const float A0 = fmaf(-g.rv0, inv_rvs, g.cv + 0.015625f);
+    const float V0f = (float)V0, VS1f = (float)VS1;
+    for (int cls = 0; cls < 2; ++cls) {
         int c_lo, c_hi;   // this axis' columns, intersected below
         float fp, qv;
         float u1, u2, lam;
@@ -140,18 +152,15 @@ for (int cls = 0; cls < 2; ++cls) {
             const float t = fmaf(fp, cq.w, cq.z);
             const float beta = t * g.rvs;
             const float rt = __builtin_amdgcn_rcpf(t);
-            // row where the ray crosses z index kk - 1, plus 1/64: vA + kk vB
-            const float vB = rt * inv_rvs;
-            const float vA = fmaf(fmaf(-1.0f - g.Kb, rt, -g.rv0), inv_rvs, g.cv + 0.015625f);
             const float *ycol = yt + ((u - U0) * HS - V0) * C;
 #pragma unroll
             for (int n = 0; n < KV; ++n) {
-                const float kk = (float)(k0 + n);
-                // a start moved down to VS1 only adds rows below the run
-                // (zero weight)
-                const int vs = min(max((int)floorf(fmaf(kk, vB, vA)), V0), VS1);
-                float s = fmaf(t, fmaf((float)vs - g.cv, g.rvs, g.rv0), g.Kb - kk);
-                const float *py = ycol + vs * C;
+                // run start, clamped into [V0, VS1] (a start moved down to
+                // VS1 only adds rows below the run, of zero weight)
+                const float vsf =
+                    __builtin_amdgcn_fmed3f(floorf(fmaf(rt, Bk[n], A0)), V0f, VS1f);
+                float s = fmaf(t, fmaf(vsf - g.cv, g.rvs, g.rv0), KbK[n]);
+                const float *py = ycol + (int)vsf * C;
                 float csum[C];
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch)

@@ -292,10 +292,9 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
                         for kk in range(k0, k1 + 1):
                             rows_sup = np.nonzero(np.abs(kf.astype(np.float64) - kk) < 1.0)[0]
                             inv_rvs = f32(f32(1.0) / rvs)
-                            vB = f32(rt * inv_rvs)
-                            vA = fma32(fma32(f32(-1.0) - Kb, rt, -rv0), inv_rvs,
-                                       f32(cv + f32(0.015625)))
-                            vf = fma32(f32(kk), vB, vA)
+                            Bk = f32(f32(f32(f32(kk) - f32(1.0)) - Kb) * inv_rvs)
+                            A0 = fma32(-rv0, inv_rvs, f32(cv + f32(0.015625)))
+                            vf = fma32(rt, Bk, A0)
                             vstart = min(max(int(np.floor(vf)), V0), VS1)
                             assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)
                                           & (rows_sup <= V1)), \
