@@ -45,7 +45,7 @@ constexpr int kBI = 8, kBJ = 8;
 struct BrickArgs {
     DevGeom g;
     const BrickWin *wins;  // [n_angles][nby][nbx] panel windows
-    int W, H, HS, NTmax;   // window columns and rows, LDS column stride (odd), taps
+    int W, H, HS, NTmax;   // window columns and rows, LDS column stride, taps
     int nbx, nby, nbz;
     int KV;                // voxels per thread along z (bricks 8 x 8 x 4 KV)
 };
@@ -189,8 +189,8 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&acc)[KV
 // ys[c] is channel c's sinogram, vols[c] its volume.  Bricks are 8 x 8 x 4 KV
 // voxels; thread (lane, wave w) owns voxel column (lane % 8, lane / 8) and
 // the KV voxels from 4 KV (brick z) + KV w up.  `lds` holds the panel window,
-// column-major with C channels per element ([W][HS][C], HS odd so that a row
-// of lanes writes distinct banks), and the column table.
+// column-major with C channels per element ([W][HS][C], HS = 2 mod 4, which
+// suits the gather's reads), and the column table.
 template <class SS, class VS, int C, int KV>
 __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
                                              const typename SS::T *const (&ys)[C],

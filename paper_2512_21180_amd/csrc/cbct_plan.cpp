@@ -218,9 +218,12 @@ AdjPlan adjoint_plan(const cbct_geom *g, const WinTable &t, int bk, int channels
     // a tap run never leaves the window (its start is clamped), so the
     // window needs the brick's rows, or one run when that is taller
     H = std::max(H, NT);
-    // the window is stored column-major with an odd column stride, so a row
-    // of lanes writing consecutive columns hits distinct LDS banks
-    int WS = H | 1;
+    // the window is stored column-major; a column stride of 2 mod 4 words
+    // spreads the gather's reads (lanes of a wave read different columns)
+    // over the LDS banks best: at the clinical size 23.0 ms for the adjoint
+    // against 24.0 ms with odd strides, which would instead spare the
+    // staging's row writes a two-way conflict
+    int WS = H + (6 - H % 4) % 4;
     size_t lds = (size_t)W * WS * channels * sizeof(float) + (size_t)W * 4 * sizeof(float);
     if (W > 0 && lds <= budget && NT <= kMaxTaps) {
         p.ok = true;

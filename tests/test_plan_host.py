@@ -258,7 +258,7 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
         assert V1 == V1u
         Hs = max(V1 - V0 + 1, NT)
         VS1 = max(V1 - NT + 1, V0)
-        assert U1 - U0 + 1 <= W_ and Hs <= H_ and H_ <= WS and WS % 2 == 1
+        assert U1 - U0 + 1 <= W_ and Hs <= H_ and H_ <= WS and WS % 4 == 2
         for i in range(i0, i1 + 1):
             for j in range(j0, j1 + 1):
                 for cls in (0, 1):
