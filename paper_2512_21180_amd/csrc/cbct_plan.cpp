@@ -246,7 +246,11 @@ void plan_host(cbct_geom *g)
     g->tiles.clear();
     TileBuild tb;
     int R = 0, TU = 64;
+    // the tiled kernel addresses one volume channel with 32-bit byte offsets
+    const bool off32 = (uint64_t)d.nx * d.ny * d.nz * sizeof(float) < (1ull << 32);
     for (int tu : {64, 32}) {
+        if (!off32)
+            break;
         for (int r : {8, 4, 2, 1}) {
             tb = make_tiles(g, tu, (256 / tu) * r);
             if (tb.BQ <= kMaxBoxQ && tb.BK <= kMaxBoxK) {

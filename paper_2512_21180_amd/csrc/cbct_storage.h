@@ -1,6 +1,7 @@
 // Storage conversions for the projector kernels: FP32 arithmetic on FP32,
 // BF16 or FP16 buffers (widened on load, rounded to nearest-even on store).
-// `raw` loads the stored bits into a 32-bit register and `wide` widens them:
+// `raw` loads the stored bits into a 32-bit register (`raw_at`: at a 32-bit
+// byte offset from the base) and `wide` widens them:
 // a kernel that keeps loads in flight across other work holds raw values and
 // widens them where they are used (widening, or packing two 16-bit values
 // into one register, right after the load would wait for it).
@@ -17,6 +18,10 @@ struct F32 {
     __device__ static float ld(const T *p, size_t i) { return p[i]; }
     using Raw = float;
     __device__ static Raw raw(const T *p, size_t i) { return p[i]; }
+    __device__ static Raw raw_at(const T *p, uint32_t byte_off)
+    {
+        return *(const T *)((const char *)p + byte_off);
+    }
     __device__ static float wide(Raw x) { return x; }
     __device__ static void st(T *p, size_t i, float v) { p[i] = v; }
 };
@@ -26,6 +31,10 @@ struct BF16 {
     using Raw = uint32_t;
     __device__ static float ld(const T *p, size_t i) { return wide(p[i]); }
     __device__ static Raw raw(const T *p, size_t i) { return p[i]; }
+    __device__ static Raw raw_at(const T *p, uint32_t byte_off)
+    {
+        return *(const T *)((const char *)p + byte_off);
+    }
     __device__ static float wide(Raw x) { return __uint_as_float(x << 16); }
     __device__ static void st(T *p, size_t i, float v)
     {
@@ -46,6 +55,10 @@ struct F16 {
     __device__ static Raw raw(const T *p, size_t i)
     {
         return __builtin_bit_cast(uint16_t, p[i]);
+    }
+    __device__ static Raw raw_at(const T *p, uint32_t byte_off)
+    {
+        return __builtin_bit_cast(uint16_t, *(const T *)((const char *)p + byte_off));
     }
     __device__ static float wide(Raw x)
     {
