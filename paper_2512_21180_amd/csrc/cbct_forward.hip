@@ -11,8 +11,9 @@
 //
 // The tile sweeps the voxel-centre planes of its axis.  On plane p every ray
 // of the tile lands inside a box of at most 64 (in-plane) x 32 (z) voxels
-// spanned by the corner rays; the box is staged in LDS (zero outside the
-// volume) one plane ahead of its use, double-buffered, one barrier per plane.
+// spanned by the corner rays (the boxes of all planes are tabulated in LDS
+// at the tile's start); the box is staged in LDS (zero outside the volume)
+// one plane ahead of its use, double-buffered, one barrier per plane.
 // Each sample is the bilinear interpolant read from LDS; each ray keeps its
 // own running sum in a register, so the summation order is the plane order
 // whatever the launch shape, and the result is written once, coalesced along
@@ -33,6 +34,9 @@ constexpr int kMaxR = 8;       // rays per thread
 constexpr int kQS = 65;        // LDS row stride (floats): box rows are <= 64 wide
 constexpr int kMaxRows = 32;   // box rows (z) per plane
 constexpr int kSlots = kMaxRows / 4;
+constexpr int kBoxChunk = 256; // planes whose boxes are tabulated at a time
+// LDS: two staging boxes, then the box table (one int4 per plane of a chunk)
+constexpr size_t kFwdLds = 2 * (size_t)kMaxRows * kQS * sizeof(float) + kBoxChunk * 16;
 
 // Sweep one tile.  R (rays per thread, 1..8) is uniform per tile; the per
 // ray arithmetic does not depend on it, so any launch shape gives the same
@@ -85,20 +89,31 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     struct Box {
         int qlo, klo, qw, kw;
     };
-    auto box_of = [&](int p) {
-        const float fp = (float)p;
-        const float qa = fmaf(fp, cA.ps, cA.pb), qb = fmaf(fp, cB.ps, cB.pb);
-        const float k0 = fmaf(fp, ksA0, kbA0), k1 = fmaf(fp, ksA1, kbA1);
-        const float k2 = fmaf(fp, ksB0, kbB0), k3 = fmaf(fp, ksB1, kbB1);
+    // The box of every plane is computed once per tile, one plane per
+    // thread, into an LDS table of kBoxChunk planes (refilled when the sweep
+    // passes a chunk); the sweep reads it back as wave-uniform values.
+    int4 *boxes = (int4 *)(lds + 2 * kMaxRows * kQS);
+    auto fill_boxes = [&](int base) {
+        const int p = base + tid;
+        if (p <= T.p_hi) {
+            const float fp = (float)p;
+            const float qa = fmaf(fp, cA.ps, cA.pb), qb = fmaf(fp, cB.ps, cB.pb);
+            const float k0 = fmaf(fp, ksA0, kbA0), k1 = fmaf(fp, ksA1, kbA1);
+            const float k2 = fmaf(fp, ksB0, kbB0), k3 = fmaf(fp, ksB1, kbB1);
+            const int qlo = (int)floorf(fminf(qa, qb)) - 1;
+            const int klo = (int)floorf(fminf(fminf(k0, k1), fminf(k2, k3))) - 1;
+            const int qw = min((int)floorf(fmaxf(qa, qb)) + 3 - qlo, 64);
+            const int kw = min((int)floorf(fmaxf(fmaxf(k0, k1), fmaxf(k2, k3))) + 3 - klo, kMaxRows);
+            boxes[tid] = make_int4(qlo, klo, qw, kw);
+        }
+    };
+    auto box_of = [&](int p, int base) {
+        const int4 v = boxes[p - base];
         Box b;
-        b.qlo = (int)floorf(fminf(qa, qb)) - 1;
-        b.klo = (int)floorf(fminf(fminf(k0, k1), fminf(k2, k3))) - 1;
-        b.qw = min((int)floorf(fmaxf(qa, qb)) + 3 - b.qlo, 64);
-        b.kw = min((int)floorf(fmaxf(fmaxf(k0, k1), fmaxf(k2, k3))) + 3 - b.klo, kMaxRows);
-        b.qlo = __builtin_amdgcn_readfirstlane(b.qlo);
-        b.klo = __builtin_amdgcn_readfirstlane(b.klo);
-        b.qw = __builtin_amdgcn_readfirstlane(b.qw);
-        b.kw = __builtin_amdgcn_readfirstlane(b.kw);
+        b.qlo = __builtin_amdgcn_readfirstlane(v.x);
+        b.klo = __builtin_amdgcn_readfirstlane(v.y);
+        b.qw = __builtin_amdgcn_readfirstlane(v.z);
+        b.kw = __builtin_amdgcn_readfirstlane(v.w);
         return b;
     };
     // stored values stay raw until the LDS store, so the loads of the next
@@ -128,11 +143,13 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     };
 
     __syncthreads();   // the previous work item's readers of lds are done
-    int p = T.p_lo;
+    int p = T.p_lo, base = T.p_lo;
+    fill_boxes(base);
+    __syncthreads();
     Box nb{0, 0, 0, 0};
     Raw stage[kSlots];
     if (p <= T.p_hi) {
-        nb = box_of(p);
+        nb = box_of(p, base);
         fetch(p, nb, stage);
     }
     for (; p <= T.p_hi; ++p) {
@@ -144,7 +161,12 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
                 buf[(w + 4 * s) * kQS + lane] = VS::wide(stage[s]);
         __syncthreads();
         if (p < T.p_hi) {
-            nb = box_of(p + 1);
+            if (p + 1 - base == kBoxChunk) {   // uniform: next chunk of boxes
+                base += kBoxChunk;
+                fill_boxes(base);   // every reader of the old chunk is past the barrier
+                __syncthreads();
+            }
+            nb = box_of(p + 1, base);
             fetch(p + 1, nb, stage);
         }
         const float fp = (float)p;
@@ -257,7 +279,7 @@ hipError_t launch_forward_tiled(const DevGeom &g, const FwdPlan &p, const void *
                                 hipStream_t s)
 {
     SweepArgs A{g, p.tiles, p.R, p.TU == 32 ? 5 : 6};
-    const size_t lds = 2 * (size_t)kMaxRows * kQS * sizeof(float);
+    const size_t lds = kFwdLds;
     dim3 grid(p.n_tiles, channels), block(kThreads);
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
@@ -281,7 +303,7 @@ hipError_t launch_forward_batch(int n, const cbct_geom *const *gs, const void *c
         B.c[i] = FwdCase{g->dev, g->fwd.tiles, g->fwd.R, g->fwd.TU == 32 ? 5 : 6,
                          g->fwd.n_tiles, vols[i], sinos[i]};
         items += g->fwd.n_tiles;
-        lds = 2 * (size_t)kMaxRows * kQS * sizeof(float);
+        lds = kFwdLds;
     }
     B.first[n] = items;
     B.n_items = items;

@@ -71,6 +71,9 @@ SHORT_BRICKS_1 = W.geometry(10, 150, 170, 0.8, 0.8, 20, 18, 23, 5.0, off_u=20.0)
 # 2 mm pixels over 1 mm voxels: 64 columns of rays spread over more than 64
 # voxels, the forward takes 32-column tiles (two row groups per wave)
 NARROW_TILES = W.geometry(12, 70, 50, 2.0, 2.0, 40, 36, 30, 1.0, off_u=10.0)
+# 300 planes along x: the forward's tiles sweep more planes than one table
+# of plane boxes holds (256), so the table is refilled mid-sweep
+LONG_SWEEP = W.geometry(6, 48, 24, 1.6, 1.6, 300, 40, 20, 1.0, off_u=5.0)
 CASES = {
     "fallback_fwd": FINE_VOX,
     "fallback_adj": COARSE_VOX,
@@ -81,6 +84,7 @@ CASES = {
     "short_bricks_8": SHORT_BRICKS_2,
     "short_bricks_4": SHORT_BRICKS_1,
     "narrow_tiles": NARROW_TILES,
+    "long_sweep": LONG_SWEEP,
 }
 
 

@@ -376,3 +376,17 @@ def test_brick_depth_follows_the_window():
                 assert lds <= 40 * 1024 or h.info[10] == 1
         finally:
             h.close()
+
+
+def test_tiled_forward_needs_32bit_offsets():
+    """The tiled forward addresses a volume channel with 32-bit byte offsets:
+    volumes of 4 GiB or more (FP32) take the one-thread-per-ray kernel."""
+    small = W.geometry(4, 64, 16, 0.1, 0.1, 1024, 1024, 1023, 0.2)
+    big = W.geometry(4, 64, 16, 0.1, 0.1, 1024, 1024, 1024, 0.2)
+    hs, hb = Host(small), Host(big)
+    try:
+        assert hs.info[0] == 1
+        assert hb.info[0] == 0
+    finally:
+        hs.close()
+        hb.close()
