@@ -14,7 +14,9 @@
 // then columns, then rows), so every voxel is written once and no atomics
 // are needed.  For each angle the brick's panel window is staged in LDS,
 // pre-multiplied by the ray length per plane ds, together with the column
-// constants.  Per voxel and column, the rows with non-zero weight lie above
+// constants; the window's columns, the source-panel scales that give its
+// rows and the row taps NT come from a table the host computes in FP64 per
+// angle and brick column.  Per voxel and column, the rows with non-zero weight lie above
 // the row v_c where the ray crosses z = k - 1 and span less than 2 / beta
 // rows (beta: rows to z index, at least that of the brick's nearest point
 // to the source); the run of NT = floor(2 / beta) + 2 rows that starts at
@@ -45,7 +47,7 @@ constexpr int kBI = 8, kBJ = 8;
 struct BrickArgs {
     DevGeom g;
     const BrickWin *wins;  // [n_angles][nby][nbx] panel windows
-    int W, H, HS, NTmax;   // window columns and rows, LDS column stride, taps
+    int W, H, HS;          // window columns and rows, LDS column stride
     int nbx, nby, nbz;
     int KV;                // voxels per thread along z (bricks 8 x 8 x 4 KV)
 };
@@ -53,9 +55,9 @@ struct BrickArgs {
 __device__ inline float sat(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
 // Fractional panel column of the ray through (x, y, .) and its source-panel
-// scale lambda (a point at height z lands at V = lambda z).  Used only to
-// bound windows (every bound carries a margin), so approximate reciprocals
-// are enough.
+// scale lambda (a point at height z lands at V = lambda z).  Used only for a
+// voxel's column range, which is widened to whole columns and trimmed by the
+// exact weights, so approximate reciprocals are enough.
 __device__ inline void project_xy(const DevGeom &g, float inv_du, float c, float s, float x,
                                   float y, float &u, float &lam)
 {
@@ -447,7 +449,7 @@ adjoint_batch(BatchAdjArgs B)
 static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
 {
     const int bk = 4 * p.KV;
-    return BrickArgs{g, p.wins, p.W, p.H, p.WS, p.NTmax, (g.nx + kBI - 1) / kBI,
+    return BrickArgs{g, p.wins, p.W, p.H, p.WS, (g.nx + kBI - 1) / kBI,
                      (g.ny + kBJ - 1) / kBJ, (g.nz + bk - 1) / bk, p.KV};   // WS: column stride
 }
 

@@ -40,7 +40,7 @@ constexpr size_t kFwdLds = 2 * (size_t)kMaxRows * kQS * sizeof(float) + kBoxChun
 
 // Sweep one tile.  R (rays per thread, 1..8) is uniform per tile; the per
 // ray arithmetic does not depend on it, so any launch shape gives the same
-// bits.  `lds` holds two boxes of kMaxRows x kQS floats.
+// bits.  `lds` holds two boxes of kMaxRows x kQS floats and the box table.
 //
 // On plane p the box spans in-plane indices [qlo, qlo + qw) and z indices
 // [klo, klo + kw), from the corner rays' crossings widened by one voxel for

@@ -9,12 +9,15 @@
 // or the last plane), widened by the rounding margins the kernel relies on.
 // TU is 64 columns, or 32 where 64 columns of rays spread wider than 64
 // voxels (pixels coarser than the voxels); TV is the largest of 256 / TU
-// times 8, 4, 2, 1 rows whose boxes fit.
+// times 8, 4, 2, 1 rows whose boxes fit.  Volumes of 4 GiB or more (the
+// kernel's offsets are 32-bit) take the one-thread-per-ray kernel.
 //
 // Adjoint: the volume is cut into 8 x 8 x 4 KV bricks (KV = 4, 2 or 1 voxels
 // per thread along z).  For every angle a brick's support (voxel centres +-
 // one pitch) projects onto the panel inside a W x H window that is staged in
-// LDS; W and H are the largest windows over all bricks and angles.  The
+// LDS; W and H are the largest windows over all bricks and angles.  Each
+// brick column's window (columns, source-panel scales, row taps) is
+// tabulated per angle for the kernel.  The
 // tallest bricks whose window lets four workgroups share a CU's 160 KB of LDS
 // and that still give two bricks per CU are taken (small volumes take
 // shorter bricks to fill the chip), else the tallest that fit 64 KB (large
