@@ -20,17 +20,41 @@ def sources():
     return sorted(glob.glob(os.path.join(csrc, "*.cpp")) + glob.glob(os.path.join(csrc, "*.hip")))
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile every source under csrc/ into paper_2512_21180_amd/libcbct.so."""
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + sources()
+def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + msgs)
-    if verbose and msgs.strip():
-        print(msgs)
+    return msgs
+
+
+def build_library(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source under csrc/ into paper_2512_21180_amd/libcbct.so:
+    one object per source, compiled in parallel (`jobs` processes, default
+    the CPU count up to 8), then one link."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include")]
+    cflags = [f for f in HIP_FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        return obj, _run([hipcc] + cflags + inc + ["-c", "-o", obj, src])
+
+    n = jobs or min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        results = list(ex.map(compile_one, sources()))
+    tmp = LIB + ".tmp"
+    msgs = [m for _, m in results] + [
+        _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] +
+             [o for o, _ in results])]
+    if verbose:
+        text = "\n".join(m for m in msgs if m.strip())
+        if text:
+            print(text)
     os.replace(tmp, LIB)
     return LIB
 
