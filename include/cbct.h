@@ -120,7 +120,10 @@ cbct_status cbct_geom_sizes(const cbct_geom *g, uint64_t *n_vox, uint64_t *n_sin
 
 /*
  * sino = A vol for n_channels >= 1 stacked channels.  vol (storage vt) is
- * [C][nz][ny][nx]; sino (storage st) is [C][n_angles][nv][nu].
+ * [C][nz][ny][nx]; sino (storage st) is [C][n_angles][nv][nu].  Geometries
+ * whose ray tiles spread over more voxels than the tiled kernel stages, or
+ * whose volume channel takes 4 GiB or more in FP32, run a one-thread-per-ray
+ * kernel with the same arithmetic (slower; cbct_geom_plan_info tells which).
  */
 cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,
                          void *sino, cbct_dtype st, int n_channels, void *stream);
@@ -128,7 +131,9 @@ cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,
 /*
  * vol = A^T sino for n_channels >= 1 stacked channels (layouts as above).
  * The weights are the ones cbct_forward applies, so the two are transposes
- * up to FP32 rounding of the sums.
+ * up to FP32 rounding of the sums.  Geometries whose panel windows exceed
+ * 64 KB of LDS even for 8 x 8 x 4 voxel bricks run a one-thread-per-voxel
+ * kernel with the same weights (slower).
  */
 cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
                          void *vol, cbct_dtype vt, int n_channels, void *stream);
