@@ -290,11 +290,54 @@ def secondary_workload(name, steps, warmup):
     }
 
 
+def measure_peaks():
+    """Measured ceilings of the three resources, next to the published ones:
+    FP32 FMA issue (lane-operations/s, 8 independent chains per thread on
+    8 workgroups per CU), conflict-free LDS reads (bytes/s) and a 1 GiB
+    device-to-device copy (read + write bytes/s)."""
+    import torch
+    from paper_2512_21180_amd import cbct
+
+    nb, th = 256 * 8, cbct.probe_threads()
+    out = torch.empty(nb * th, dtype=torch.float32, device="cuda")
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    it_v, it_l = 20000, 5000
+    t_v = timed(lambda: cbct.probe_valu(nb, it_v, out))
+    t_l = timed(lambda: cbct.probe_lds(nb, it_l, out))
+    src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    t_c = timed(lambda: dst.copy_(src))
+    valu = nb * th * it_v * 8 / t_v / 1e12
+    lds = nb * th * it_l * 64 / t_l / 1e12
+    hbm = 2 * src.numel() * 4 / t_c / 1e12
+    return {
+        "valu_fma": {"measured": round(valu, 2), "published": round(VALU_PEAK_TOPS, 2),
+                     "unit": "T lane-ops/s", "frac_of_published": round(valu / VALU_PEAK_TOPS, 3)},
+        "lds_read": {"measured": round(lds, 2), "unit": "TB/s",
+                     "per_cu_bytes_per_clock": round(lds * 1e12 / 256 / 2.4e9, 1)},
+        "hbm_copy": {"measured": round(hbm, 2), "published": 8.0, "unit": "TB/s",
+                     "frac_of_published": round(hbm / 8.0, 3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure FMA issue, LDS read and device-copy rates instead")
     ap.add_argument("--workload", default="c2", choices=("c2", "c2-bf16", "c1", "c3", "c4"),
                     help="case to time (default: the clinical-size FP32 case)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -324,6 +367,9 @@ def main():
     from paper_2512_21180_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.peaks:
+        print(json.dumps(measure_peaks()), flush=True)
+        return
     if args.workload != "c2":
         print(json.dumps(secondary_workload(args.workload, args.steps, args.warmup)), flush=True)
         return

@@ -83,6 +83,10 @@ def _load():
     lib.cbct_fdk.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.cbct_conv1.argtypes = [sz, i32, ctypes.POINTER(vp), vp, vp, i32, fl, vp]
     lib.cbct_fov_fraction.argtypes = [vp, vp]
+    lib.cbct_probe_threads.argtypes = []
+    lib.cbct_probe_threads.restype = i32
+    lib.cbct_probe_valu.argtypes = [i32, i32, vp, vp]
+    lib.cbct_probe_lds.argtypes = [i32, i32, vp, vp]
     lib.cbct_error_string.argtypes = [i32]
     lib.cbct_error_string.restype = ctypes.c_char_p
     lib.cbct_last_hip_error.argtypes = []
@@ -94,7 +98,7 @@ def _load():
                  "cbct_philox_blocks", "cbct_sim_poisson_log", "cbct_sim_gaussian",
                  "cbct_pack16", "cbct_conv3", "cbct_conv3_wgrad", "cbct_conv1", "cbct_wresid",
                  "cbct_pool", "cbct_projdown", "cbct_upsample", "cbct_fdk",
-                 "cbct_fov_fraction"):
+                 "cbct_fov_fraction", "cbct_probe_valu", "cbct_probe_lds"):
         getattr(lib, name).restype = i32
     return lib
 
@@ -547,3 +551,28 @@ def fdk(geom: Geometry, sino: torch.Tensor, out: torch.Tensor | None = None,
         _check(_lib.cbct_fdk(geom.handle, _f32(sino, "sino"), win, _f32(work, "work"),
                              _f32(out, "out"), _stream(geom.device)), "cbct_fdk")
     return out
+
+
+# ---- peak probes (diagnostics) ----------------------------------------------
+
+def probe_threads() -> int:
+    return int(_lib.cbct_probe_threads())
+
+
+def probe_valu(n_blocks: int, iters: int, out: torch.Tensor):
+    """Launch the FMA-issue probe (8 FMA chains per thread, iters steps);
+    out: float32 CUDA tensor of n_blocks * probe_threads() elements.
+    Lane FMAs = n_blocks * probe_threads() * iters * 8."""
+    if out.numel() < n_blocks * probe_threads():
+        raise ValueError("out too small")
+    _check(_lib.cbct_probe_valu(int(n_blocks), int(iters), _f32(out, "out"),
+                                _stream(out.device)), "cbct_probe_valu")
+
+
+def probe_lds(n_blocks: int, iters: int, out: torch.Tensor):
+    """Launch the LDS-read probe (four conflict-free 16-byte reads per
+    thread and step); LDS bytes = n_blocks * probe_threads() * iters * 64."""
+    if out.numel() < n_blocks * probe_threads():
+        raise ValueError("out too small")
+    _check(_lib.cbct_probe_lds(int(n_blocks), int(iters), _f32(out, "out"),
+                               _stream(out.device)), "cbct_probe_lds")
