@@ -241,8 +241,8 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
         // the table, rows from the extreme source-panel scales (positive) at
         // the support's lowest and highest z
         const BrickWin bw = wcol[(size_t)a * wstep];
-        const int U0 = bw.u01 & 0xffff;
-        const int U1 = min(bw.u01 >> 16, U0 + A.W - 1);
+        const int U0 = (int)(bw.u01 & 0xffffu);
+        const int U1 = min((int)(bw.u01 >> 16), U0 + A.W - 1);
         if (U0 > U1)
             continue;
         const float lmin = bw.lmin, lmax = bw.lmax;

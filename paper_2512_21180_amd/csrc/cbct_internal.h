@@ -96,7 +96,7 @@ __host__ __device__ inline int adj_taps_rounded(int nt)
 // row taps per voxel and column its rays need.
 struct BrickWin {
     float lmin, lmax;
-    int u01;           // u0 | u1 << 16
+    uint32_t u01;      // u0 | u1 << 16 (columns below 65536)
     int nt;
 };
 static_assert(sizeof(BrickWin) == 16, "BrickWin layout");

@@ -173,10 +173,10 @@ WinTable brick_windows(const cbct_geom *g, int NTmax)
                 bw.lmin = (float)lmin;
                 bw.lmax = (float)lmax;
                 if (u0 <= u1) {
-                    bw.u01 = u0 | (u1 << 16);
+                    bw.u01 = (uint32_t)u0 | ((uint32_t)u1 << 16);
                     t.W = std::max(t.W, u1 - u0 + 1);
                 } else {
-                    bw.u01 = 1;   // u0 = 1 > u1 = 0: not seen
+                    bw.u01 = 1u;   // u0 = 1 > u1 = 0: not seen
                 }
                 const int nt = (int)std::floor(2.0 / (tmin * rvs)) + 2;
                 bw.nt = adj_taps_rounded(std::min(nt, NTmax));
@@ -201,7 +201,7 @@ AdjPlan adjoint_plan(const cbct_geom *g, const WinTable &t, int bk, int channels
     const int nbz = (d.nz + bk - 1) / bk;
     auto cz = [&](double k) { return d.origin_mm[2] + (k - 0.5 * (d.nz - 1)) * d.vz_mm; };
     for (size_t e = 0; e < t.w.size(); ++e) {
-        if ((t.w[e].u01 & 0xffff) > (t.w[e].u01 >> 16))
+        if ((t.w[e].u01 & 0xffffu) > (t.w[e].u01 >> 16))
             continue;
         const double lmin = t.lmin[e], lmax = t.lmax[e];
         for (int bz = 0; bz < nbz; ++bz) {

@@ -74,6 +74,9 @@ NARROW_TILES = W.geometry(12, 70, 50, 2.0, 2.0, 40, 36, 30, 1.0, off_u=10.0)
 # 300 planes along x: the forward's tiles sweep more planes than one table
 # of plane boxes holds (256), so the table is refilled mid-sweep
 LONG_SWEEP = W.geometry(6, 48, 24, 1.6, 1.6, 300, 40, 20, 1.0, off_u=5.0)
+# a 40000-column panel whose volume projects near column 35000: the
+# adjoint's window columns (packed 16 + 16 bits) lie above 32767
+WIDE_PANEL = W.geometry(3, 40000, 16, 0.01, 0.01, 16, 16, 8, 0.05, off_u=-150.0)
 CASES = {
     "fallback_fwd": FINE_VOX,
     "fallback_adj": COARSE_VOX,
@@ -85,6 +88,7 @@ CASES = {
     "short_bricks_4": SHORT_BRICKS_1,
     "narrow_tiles": NARROW_TILES,
     "long_sweep": LONG_SWEEP,
+    "wide_panel": WIDE_PANEL,
 }
 
 

@@ -67,7 +67,7 @@ class Host:
         nbx, nby = -(-g["nx"] // 8), -(-g["ny"] // 8)
         self.win_l = wins.view(np.float32).reshape(g["n_angles"], nby, nbx, 4)[..., :2] \
             if wins.size else None
-        self.win_i = wins.view(np.int32).reshape(g["n_angles"], nby, nbx, 4)[..., 2:] \
+        self.win_i = wins.view(np.uint32).reshape(g["n_angles"], nby, nbx, 4)[..., 2:] \
             if wins.size else None
         sc = self.table(4, np.uint8)
         self.ints = sc[:24].view(np.int32)
@@ -390,3 +390,22 @@ def test_tiled_forward_needs_32bit_offsets():
     finally:
         hs.close()
         hb.close()
+
+
+def test_window_columns_pack_above_32767():
+    """The adjoint's window table packs the column range into 16 + 16 bits,
+    read unsigned: a 40000-column panel keeps its right half."""
+    g = W.geometry(3, 40000, 16, 0.01, 0.01, 16, 16, 8, 0.05, off_u=-150.0)
+    h = Host(g)
+    try:
+        assert h.info[5] == 1
+        u01 = h.win_i[..., 0].astype(np.int64)
+        seen = (u01 & 0xFFFF) <= (u01 >> 16)
+        assert seen.any()
+        u1 = (u01 >> 16)[seen]
+        assert u1.max() >= 32768 and u1.max() < 40000
+        # every seen window is inside the panel and no wider than planned
+        assert np.all((u01 & 0xFFFF)[seen] <= u1)
+        assert np.all(u1 - (u01 & 0xFFFF)[seen] + 1 <= h.info[6])
+    finally:
+        h.close()
