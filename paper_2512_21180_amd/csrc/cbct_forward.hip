@@ -35,6 +35,7 @@ constexpr int kQS = 65;        // LDS row stride (floats): box rows are <= 64 wi
 constexpr int kMaxRows = 32;   // box rows (z) per plane
 constexpr int kSlots = kMaxRows / 4;
 constexpr int kBoxChunk = 256; // planes whose boxes are tabulated at a time
+static_assert(kBoxChunk == kThreads, "the box table is filled one plane per thread");
 // LDS: two staging boxes, then the box table (one int4 per plane of a chunk)
 constexpr size_t kFwdLds = 2 * (size_t)kMaxRows * kQS * sizeof(float) + kBoxChunk * 16;
 
