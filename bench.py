@@ -37,10 +37,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A+A^T Gsamples/s at 256³×360×512²; recon s to fixed PSNR, learned vs CGLS"
 
-# Algorithmic FP32 VALU lane-operations per sample: two FMAs for the in-plane
-# and z coordinates, two floors and two fraction subtractions, three linear
-# interpolations (subtract + FMA each) and one accumulation.
-OPS_PER_SAMPLE = 14
+# Algorithmic VALU lane-operations per sample (one bilinear sample on a
+# voxel-centre plane, the unit of both operators):
+#   2  FMAs for the in-plane and z fractional indices,
+#   2  floors,
+#   2  fraction subtractions,
+#   6  three linear interpolations (subtract + FMA each),
+#   1  FMA accumulating the sample into the ray (or voxel) sum,
+#   2  integer operations forming the voxel address,
+#   -- 15 in all.
+OPS_PER_SAMPLE = 15
 # Non-packed FP32 VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -146,33 +152,83 @@ def recon_comparison(seed=50_000):
     }
 
 
-def cpu_baseline(g, n_angles=72):
-    """The FP64 oracle on the same geometry restricted to n_angles of its
-    angles (every n/n_angles-th), forward then adjoint."""
-    import numpy as np
-    from oracle import oracle as orc
-    from paper_2512_21180_amd import workloads as W
-
+def _oracle_pair(orc, g, x, n_angles, threads):
+    """Time the FP64 oracle's forward then scatter adjoint on g restricted to
+    n_angles of its angles (every n/n_angles-th); returns (samples, tA, tAT)."""
     all_ang = orc.angles_of(g)
     step = max(1, g["n_angles"] // n_angles)
     sub = dict(g, n_angles=len(all_ang[::step][:n_angles]), angles=all_ang[::step][:n_angles])
-    x, _, _ = W.phantom_c2(g, 2025)
     S = orc.sample_count(sub)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     y = orc.forward(sub, x, nthreads=threads)
     t1 = time.perf_counter()
     orc.adjoint(sub, y, nthreads=threads)
     t2 = time.perf_counter()
-    del np
+    return S, sub["n_angles"], t1 - t0, t2 - t1
+
+
+def cpu_baseline(g, n_angles=72, n_angles_1t=6):
+    """The FP64 oracle on the same geometry restricted to a subset of its
+    angles, forward then adjoint: on all host threads (n_angles angles) and
+    on one thread (n_angles_1t angles)."""
+    from oracle import oracle as orc
+    from paper_2512_21180_amd import workloads as W
+
+    x, _, _ = W.phantom_c2(g, 2025)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    S, na, tA, tAT = _oracle_pair(orc, g, x, n_angles, threads)
+    S1, na1, tA1, tAT1 = _oracle_pair(orc, g, x, n_angles_1t, 1)
     return {
-        "value": round(2 * S / (t2 - t0) / 1e9, 4),
+        "value": round(2 * S / (tA + tAT) / 1e9, 4),
         "unit": "Gsamples/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"FP64 oracle A then scatter A^T on the same case restricted to {sub['n_angles']} "
-                  f"of its {g['n_angles']} angles ({S} samples each); forward {t1 - t0:.1f} s, "
-                  f"adjoint {t2 - t1:.1f} s",
+        "sample": f"FP64 oracle A then scatter A^T on the same case restricted to {na} "
+                  f"of its {g['n_angles']} angles ({S} samples each); forward {tA:.1f} s, "
+                  f"adjoint {tAT:.1f} s",
+        "single_thread": {
+            "value": round(2 * S1 / (tA1 + tAT1) / 1e9, 4),
+            "unit": "Gsamples/s",
+            "cores": 1,
+            "sample": f"the same on {na1} of the {g['n_angles']} angles ({S1} samples each); "
+                      f"forward {tA1:.1f} s, adjoint {tAT1:.1f} s",
+        },
+    }
+
+
+def copy_bandwidth(reps=5):
+    """Achievable HBM bandwidth: a 1 GiB device-to-device copy (read + write
+    bytes over the HIP-event time, mean of reps), far larger than the caches."""
+    import torch
+    src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / reps * 1e-3
+    bw = 2 * src.numel() * 4 / t
+    del src, dst
+    torch.cuda.empty_cache()
+    return bw
+
+
+def gather_bound(S, elem_bytes, tA, tAT, bw):
+    """Fraction of the gather-bound HBM rate: every sample reads four voxels
+    (A) or four panel values (A^T) of elem_bytes each; F_g = those bytes per
+    second over the measured device-copy bandwidth (above 1 when staging and
+    caches serve the gathers)."""
+    b = S * 4 * elem_bytes
+    return {
+        "F_g": round(2 * b / (tA + tAT) / bw, 3),
+        "F_g_forward": round(b / tA / bw, 3),
+        "F_g_adjoint": round(b / tAT / bw, 3),
+        "gather_bytes_per_operator": b,
+        "copy_bw_TBps": round(bw / 1e12, 3),
     }
 
 
@@ -255,6 +311,7 @@ def secondary_workload(name, steps, warmup):
         dom += "_batch"
     achieved = OPS_PER_SAMPLE * S / tdom / 1e12
     elem = 2 if dtype == "bf16" else 4
+    bw = copy_bandwidth()
     return {
         "metric": "A+A^T Gsamples/s",
         "value": round(2 * S * steps / wall / 1e9, 3),
@@ -287,6 +344,7 @@ def secondary_workload(name, steps, warmup):
             "algorithmic_bytes": sum(elem * (math.prod(g.vol_shape) + math.prod(g.sino_shape))
                                      for g in geos),
         },
+        "gather_bound": gather_bound(S, elem, tA, tAT, bw),
     }
 
 
@@ -331,11 +389,71 @@ def measure_peaks():
     }
 
 
+CONV_GRIDS = {
+    "volume 256^3": (256, 256, 256),
+    "sinogram stack 360x512^2 (r=1)": (360, 512, 512),
+    "sinogram stack 90x128^2 (r=4)": (90, 128, 128),
+}
+
+
+def measure_convs(reps=5):
+    """HIP-event times of the learned blocks' 3x3x3 convolution kernels at the
+    net's real grids (16 -> 16 channels, BF16 operands, FP32 accumulation):
+    the forward (bias + LeakyReLU, BF16 channel-last store), the data
+    gradient (transposed weights + LeakyReLU-derivative mask) and the weight
+    gradient.  FLOP = 2 x 27 x 16 x 16 per position for each kernel; the
+    HBM bytes are the compulsory ones (BF16 x 16 channels read once per
+    operand, written once)."""
+    import torch
+    from paper_2512_21180_amd import cbct
+
+    gen = torch.Generator("cuda").manual_seed(0)
+    res = {}
+    for name, grid in CONV_GRIDS.items():
+        S = grid[0] * grid[1] * grid[2]
+        x = torch.randn((S, 16), device="cuda", generator=gen).to(torch.bfloat16)
+        m = torch.randn((S, 16), device="cuda", generator=gen).to(torch.bfloat16)
+        w = (0.1 * torch.randn((27, 16, 16), device="cuda", generator=gen)).to(torch.bfloat16)
+        b = torch.zeros(16, device="cuda")
+        y = torch.empty((S, 16), dtype=torch.bfloat16, device="cuda")
+        dw = torch.empty((27, 16, 16), device="cuda")
+        db = torch.empty(16, device="cuda")
+        ws = cbct.conv3_wgrad_workspace(S, "cuda")
+        runs = {
+            "conv3": (lambda: cbct.conv3(grid, x, w, bias=b, act=True, y_cl=y), 4 * 16 * S),
+            "conv3_transposed_masked": (
+                lambda: cbct.conv3(grid, x, w, mask=m, transpose_w=True, y_cl=y), 6 * 16 * S),
+            "wgrad": (lambda: cbct.conv3_wgrad(grid, x, m, dw, db, ws), 4 * 16 * S),
+        }
+        out = {}
+        for k, (fn, hbm) in runs.items():
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps * 1e-3
+            flop = 2 * 27 * 256 * S
+            out[k] = {"ms": round(t * 1e3, 3), "tflops": round(flop / t / 1e12, 1),
+                      "frac_mfma_bf16": round(flop / t / 2.5e15, 4),
+                      "compulsory_hbm_TBps": round(hbm / t / 1e12, 3)}
+        res[name] = {"positions": S, **out}
+        print(json.dumps({name: res[name]}), file=sys.stderr, flush=True)
+        del x, m, y, ws
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--convs", action="store_true",
+                    help="time the learned blocks' convolution kernels at the net's grids instead")
     ap.add_argument("--peaks", action="store_true",
                     help="measure FMA issue, LDS read and device-copy rates instead")
     ap.add_argument("--workload", default="c2", choices=("c2", "c2-bf16", "c1", "c3", "c4"),
@@ -369,6 +487,9 @@ def main():
     torch.cuda.set_device(0)
     if args.peaks:
         print(json.dumps(measure_peaks()), flush=True)
+        return
+    if args.convs:
+        print(json.dumps(measure_convs()), flush=True)
         return
     if args.workload != "c2":
         print(json.dumps(secondary_workload(args.workload, args.steps, args.warmup)), flush=True)
@@ -439,6 +560,7 @@ def main():
             "traffic": measured_traffic(dom),
             "algorithmic_bytes": algorithmic_bytes(g),
         },
+        "gather_bound": gather_bound(S, 4, tA, tAT, copy_bandwidth()),
     }
     if args.copy_calibration:
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")

@@ -179,44 +179,33 @@ adjoint_simple(DevGeom g, const typename SS::T *__restrict__ sino, typename VS::
 }  // namespace
 
 hipError_t launch_forward_simple(const DevGeom &g, const void *vol, cbct_dtype vt, void *sino,
-                          cbct_dtype st, int channels, hipStream_t s)
+                                 cbct_dtype st, int channels, hipStream_t s)
 {
     dim3 block(256);
     dim3 grid((g.nu + 255) / 256, g.nv, g.n_angles * channels);
-#define FWD(VS, SS)                                                                        \
-    hipLaunchKernelGGL((forward_simple<VS, SS>), grid, block, 0, s,                        \
-                       g, (const VS::T *)vol, (SS::T *)sino)
-    if (vt == CBCT_F32 && st == CBCT_F32) FWD(F32, F32);
-    else if (vt == CBCT_BF16 && st == CBCT_BF16) FWD(BF16, BF16);
-    else if (vt == CBCT_F16 && st == CBCT_F16) FWD(F16, F16);
-    else if (vt == CBCT_BF16 && st == CBCT_F32) FWD(BF16, F32);
-    else if (vt == CBCT_F16 && st == CBCT_F32) FWD(F16, F32);
-    else if (vt == CBCT_F32 && st == CBCT_BF16) FWD(F32, BF16);
-    else if (vt == CBCT_F32 && st == CBCT_F16) FWD(F32, F16);
-    else return hipErrorInvalidValue;
-#undef FWD
-    return hipGetLastError();
+    // every storage pair the tiled kernels accept (dispatch_storage)
+    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
+        using VS = decltype(vs);
+        using SS = decltype(ss);
+        hipLaunchKernelGGL((forward_simple<VS, SS>), grid, block, 0, s, g,
+                           (const typename VS::T *)vol, (typename SS::T *)sino);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_adjoint_simple(const DevGeom &g, const void *sino, cbct_dtype st, void *vol,
-                          cbct_dtype vt, int channels, hipStream_t s)
+                                 cbct_dtype vt, int channels, hipStream_t s)
 {
     const size_t nvox = (size_t)g.nx * g.ny * g.nz;
     dim3 block(256);
     dim3 grid((unsigned)((nvox + 255) / 256), channels);
-#define ADJ(SS, VS)                                                                        \
-    hipLaunchKernelGGL((adjoint_simple<SS, VS>), grid, block, 0, s,                        \
-                       g, (const SS::T *)sino, (VS::T *)vol)
-    if (st == CBCT_F32 && vt == CBCT_F32) ADJ(F32, F32);
-    else if (st == CBCT_BF16 && vt == CBCT_BF16) ADJ(BF16, BF16);
-    else if (st == CBCT_F16 && vt == CBCT_F16) ADJ(F16, F16);
-    else if (st == CBCT_BF16 && vt == CBCT_F32) ADJ(BF16, F32);
-    else if (st == CBCT_F16 && vt == CBCT_F32) ADJ(F16, F32);
-    else if (st == CBCT_F32 && vt == CBCT_BF16) ADJ(F32, BF16);
-    else if (st == CBCT_F32 && vt == CBCT_F16) ADJ(F32, F16);
-    else return hipErrorInvalidValue;
-#undef ADJ
-    return hipGetLastError();
+    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
+        using VS = decltype(vs);
+        using SS = decltype(ss);
+        hipLaunchKernelGGL((adjoint_simple<SS, VS>), grid, block, 0, s, g,
+                           (const typename SS::T *)sino, (typename VS::T *)vol);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace cbct

@@ -34,7 +34,8 @@ def _say(*a):
     print(*a, flush=True)
 
 
-SCALES = [(None, "zero"), ((2, 2, 1), "zero"), ((2, 2, 1), "fdk")]
+SCALES = [(None, "zero"), ((2, 2, 1), "zero"), ((2, 2, 1), "fdk"), ((4, 2, 1), "zero"),
+          ((4, 2, 1), "fdk")]
 
 
 def _setup(dev, oracle, n_iter=3, seed=0, scales=None, init="zero"):

@@ -123,3 +123,35 @@ def test_c3_batch_bf16(dev, oracle):
         e_f = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         e_a = np.linalg.norm(gota - refa) / max(np.linalg.norm(refa), 1e-30)
         print(f"  case {i}: forward rel L2 {e_f:.2e}, adjoint rel L2 {e_a:.2e}", flush=True)
+
+
+# one geometry per launch plan: tiled forward and bricked adjoint, the
+# one-thread-per-ray forward, the one-thread-per-voxel adjoint
+PLANS = {
+    "tiled": W.cropped(W.C2, n_angles=6, nv=40, n=96),
+    "fallback_fwd": W.geometry(8, 48, 40, 4.0, 4.0, 40, 40, 40, 0.25),
+    "fallback_adj": W.geometry(8, 300, 200, 0.5, 0.5, 16, 16, 16, 16.0),
+}
+
+
+@pytest.mark.parametrize("plan", sorted(PLANS))
+def test_bf16_f16_pair_on_every_plan(dev, oracle, plan):
+    """Every storage pair is accepted whatever kernels a geometry's plan
+    selects: BF16 volume -> FP16 sinogram and FP16 sinogram -> BF16 volume
+    run on the tiled/bricked and on the one-thread-per-output kernels, each
+    within the storage bound against the oracle."""
+    torch, cbct, tmap = dev
+    g = PLANS[plan]
+    print(f"[mixed] bf16<->f16 on the {plan} plan", flush=True)
+    geo = cbct.Geometry(g)
+    info = geo.plan_info()
+    print(f"  forward tiled {info['fwd_tiled']}, adjoint bricked {info['adj_bricked']}",
+          flush=True)
+    x = W.phantom_c1(g, 3)[0] + 0.01 * np.abs(W.random_volume(g, 4))
+    xg = torch.tensor(x, dtype=torch.float32, device="cuda").to(torch.bfloat16)
+    y = cbct.forward(geo, xg, out_dtype=torch.float16).double().cpu().numpy()
+    _check(y, oracle.forward(g, x), "bf16", "f16", f"{plan} forward bf16->f16")
+    s = np.abs(W.random_sino(g, 5))
+    sg = torch.tensor(s, dtype=torch.float32, device="cuda").to(torch.float16)
+    b = cbct.adjoint(geo, sg, out_dtype=torch.bfloat16).double().cpu().numpy()
+    _check(b, oracle.adjoint(g, s), "f16", "bf16", f"{plan} adjoint f16->bf16")

@@ -443,3 +443,18 @@ def test_samples_stop_at_the_pixel(oracle):
                 ds = 3.0 * np.linalg.norm(d) / abs(d[m])
                 chord = oracle.chord_box(g, a, iu, iv, lo, hi)
                 assert abs(y[a, iv, iu] - chord) <= 1.01 * ds
+
+
+def test_opnorm_equals_largest_singular_value(oracle):
+    """The power iteration's ||A||_2 (the normalisation constant of the
+    learned net's operators) equals the largest singular value of the dense
+    matrix, computed by LAPACK's SVD: a missing square root, a wrong Rayleigh
+    quotient or a missing normalisation would all miss it by far."""
+    g = tiny()
+    smax = np.linalg.norm(oracle.dense_matrix(g), 2)
+    L = oracle.opnorm(g, iters=200)
+    assert abs(L - smax) <= 1e-10 * smax
+    # a second geometry with an offset panel and another seed for the start
+    g2 = tiny(n_angles=6, off_u=-2.0)
+    smax2 = np.linalg.norm(oracle.dense_matrix(g2), 2)
+    assert abs(oracle.opnorm(g2, iters=300, seed=3) - smax2) <= 1e-10 * smax2
