@@ -16,6 +16,9 @@ Contents, each written from the paper (arXiv 2512.21180):
 * ``dense_matrix``: A built column by column from unit volumes.
 * ``cgls`` / ``landweber``: FP64 least-squares solvers on top of the oracle
   operators; Landweber uses the gradient term P*(P x - y) of Alg. 1.
+* ``water_bone`` / ``detector_response`` / ``sim_poly``: the polychromatic
+  water-bone primary model (Sec. 2.2, eq. primarymodel) and the normalised
+  negative log (Sec. 2.4, eq. normprimary).
 
 Geometry is passed as a plain dict with keys sid, sdd, n_angles, angles
 (optional, radians), nu, nv, du, dv, off_u, off_v, nx, ny, nz, vx, vy, vz,
@@ -90,6 +93,8 @@ def _load():
         lib.orc_poisson.restype = i64
         lib.orc_sim_poisson_log.argtypes = [i64, P(d), d, ctypes.c_uint64, u32, P(i64), P(d)]
         lib.orc_sim_gaussian.argtypes = [i64, P(d), d, ctypes.c_uint64, u32, P(d)]
+        lib.orc_sim_poly.argtypes = [i64, i64, P(d), P(d), ctypes.c_int, P(d), P(d), P(d), P(d),
+                                     ctypes.c_uint64, u32, P(i64), P(d), P(d)]
         _lib = lib
     return _lib
 
@@ -340,6 +345,81 @@ def sim_gaussian(clean: np.ndarray, sigma: float, seed: int, stream: int = 0) ->
     out = np.zeros_like(cc)
     lib.orc_sim_gaussian(cc.size, _dp(cc), float(sigma), seed, stream, _dp(out))
     return out.reshape(np.shape(clean))
+
+
+# ---- polychromatic water-bone primary model (Sec. 2.2) ----
+
+# Water-bone decomposition constants of Sec. 2.2.  tau_0 is not given; the
+# decomposition is stated to be continuous in the modified CT number, and
+# rho_w jumps from 0 to tau_0 at tau_0, so continuity fixes tau_0 = 0.
+TAU0, TAU1, TAU2, KAPPA_B = 0.0, 1.2, 1.6, 0.409
+
+
+def water_bone(hu: np.ndarray):
+    """(rho_w, rho_b): water and bone relative densities of a CT volume in
+    Hounsfield units, from the modified CT number rho^ = 0.001 HU + 1 by the
+    two piecewise definitions of Sec. 2.2 (FP64)."""
+    r = 0.001 * np.asarray(hu, dtype=np.float64) + 1.0
+    rw = np.zeros_like(r)
+    rb = np.zeros_like(r)
+    m1 = (r >= TAU0) & (r < TAU1)
+    m2 = (r >= TAU1) & (r < TAU2)
+    m3 = r >= TAU2
+    rw[m1] = r[m1]
+    rw[m2] = TAU1 * (TAU2 - r[m2]) / (TAU2 - TAU1)
+    rb[m2] = KAPPA_B * TAU2 * (r[m2] - TAU1) / (TAU2 - TAU1)
+    rb[m3] = KAPPA_B * r[m3]
+    return rw, rb
+
+
+def energy_bins() -> np.ndarray:
+    """Centres (keV) of the ten energy bins [10 i, 10 (i + 1)) keV, i = 2..11."""
+    return np.array([10.0 * i + 5.0 for i in range(2, 12)])
+
+
+def detector_response(e_kev) -> np.ndarray:
+    """resp(e): piecewise linear through (20, 5), (60, 20), (120, 10) keV
+    (Sec. 2.2); outside [20, 120] keV it keeps the end values."""
+    e = np.asarray(e_kev, dtype=np.float64)
+    out = np.empty_like(e)
+    lo = e <= 20.0
+    a = (e > 20.0) & (e <= 60.0)
+    b = (e > 60.0) & (e < 120.0)
+    hi = e >= 120.0
+    out[lo] = 5.0
+    out[a] = 5.0 + (e[a] - 20.0) * (20.0 - 5.0) / (60.0 - 20.0)
+    out[b] = 20.0 + (e[b] - 60.0) * (10.0 - 20.0) / (120.0 - 60.0)
+    out[hi] = 10.0
+    return out
+
+
+def sim_poly(pw: np.ndarray, pb: np.ndarray, mu_w, mu_b, resp, I0: np.ndarray, seed: int,
+             stream: int = 0):
+    """Noisy polychromatic primary projections (eq. primarymodel) and their
+    normalised negative log (eq. normprimary), given the material line
+    integrals pw = P(rho_w), pb = P(rho_b) of shape [..., nv, nu]; I0 is
+    [n_bins, nv, nu] (photons per pixel and bin, every projection alike),
+    mu_w, mu_b (mm^-1 at unit density) and resp per bin.  Returns
+    (y, signal, counts[n_bins, ...]); see orc_sim_poly for the reading of
+    zero signal and of the air scan."""
+    lib = _load()
+    shape = np.shape(pw)
+    a = np.ascontiguousarray(pw, dtype=np.float64).ravel()
+    b = np.ascontiguousarray(pb, dtype=np.float64).ravel()
+    i0 = np.ascontiguousarray(I0, dtype=np.float64)
+    nb = i0.shape[0]
+    npix = i0[0].size
+    assert a.size == b.size and a.size % npix == 0
+    mw = np.ascontiguousarray(mu_w, dtype=np.float64)
+    mb = np.ascontiguousarray(mu_b, dtype=np.float64)
+    rs = np.ascontiguousarray(resp, dtype=np.float64)
+    assert mw.size == mb.size == rs.size == nb
+    y = np.zeros_like(a)
+    sig = np.zeros_like(a)
+    c = np.zeros((nb, a.size), dtype=np.int64)
+    lib.orc_sim_poly(a.size, npix, _dp(a), _dp(b), nb, _dp(mw), _dp(mb), _dp(rs), _dp(i0.ravel()),
+                     seed, stream, _ip(c), _dp(sig), _dp(y))
+    return y.reshape(shape), sig.reshape(shape), c.reshape((nb,) + tuple(shape))
 
 
 # ---- 3x3x3 convolutions of the learned blocks (Alg. 1, dual/primal blocks) ----
