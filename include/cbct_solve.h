@@ -31,6 +31,25 @@ size_t cbct_dot_workspace(size_t n);
 cbct_status cbct_dot(size_t n, const float *a, const float *b, double *ws, double *out,
                      void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight solver loops, harnesses that forbid hipMalloc): the same
+ * dot product as cbct_dot, bitwise equal to it, with its per-block partial
+ * sums in a fixed device array of cbct_dot_noalloc_max_cells() FP64 cells
+ * (8 KiB) that the library holds on each GPU until the process ends.  No
+ * allocation happens in this call; the array's device address is looked up
+ * on the first call on each device.  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (different streams, or host threads
+ * without ordering) race and give undefined results; calls ordered on one
+ * stream are safe.  Returns CBCT_E_SHAPE if n would need more partial sums
+ * than the array holds (never, for the current fixed block count),
+ * CBCT_E_NULL for a NULL pointer, CBCT_E_HIP if the array cannot be found
+ * on the current device.  out: one device FP64 cell.
+ */
+size_t cbct_dot_noalloc_max_cells(void);
+cbct_status cbct_dot_noalloc(size_t n, const float *a, const float *b, double *out,
+                             void *stream);
+
 /* y[i] += sign * (*num / *den) * x[i], with the ratio of two device FP64
  * cells evaluated on the device (a zero denominator gives a zero step). */
 cbct_status cbct_axpy_ratio(size_t n, float *y, const float *x, const double *num,

@@ -62,6 +62,9 @@ def _load():
     lib.cbct_dot_workspace.argtypes = [sz]
     lib.cbct_dot_workspace.restype = sz
     lib.cbct_dot.argtypes = [sz, vp, vp, vp, vp, vp]
+    lib.cbct_dot_noalloc.argtypes = [sz, vp, vp, vp, vp]
+    lib.cbct_dot_noalloc_max_cells.argtypes = []
+    lib.cbct_dot_noalloc_max_cells.restype = sz
     lib.cbct_axpy_ratio.argtypes = [sz, vp, vp, vp, vp, dp, vp]
     lib.cbct_xpay_ratio.argtypes = [sz, vp, vp, vp, vp, vp]
     lib.cbct_axpby.argtypes = [sz, vp, ctypes.c_float, vp, ctypes.c_float, vp, vp]
@@ -308,6 +311,16 @@ def dot(a: torch.Tensor, b: torch.Tensor, ws: torch.Tensor, out: torch.Tensor) -
         raise ValueError("size mismatch")
     _check(_lib.cbct_dot(a.numel(), _f32(a, "a"), _f32(b, "b"), _f64cell(ws, "ws"),
                          _f64cell(out, "out"), _stream(a.device)), "cbct_dot")
+    return out
+
+
+def dot_noalloc(a: torch.Tensor, b: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """As dot(), with the library's fixed per-device partial-sum array
+    instead of a workspace (the call allocates nothing)."""
+    if a.numel() != b.numel():
+        raise ValueError("size mismatch")
+    _check(_lib.cbct_dot_noalloc(a.numel(), _f32(a, "a"), _f32(b, "b"), _f64cell(out, "out"),
+                                 _stream(a.device)), "cbct_dot_noalloc")
     return out
 
 

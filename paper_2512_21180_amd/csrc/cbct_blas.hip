@@ -5,6 +5,8 @@
 // block (FP64), then one block sums the per-block partials in index order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "cbct_internal.h"
 #include "cbct_solve.h"
 
@@ -107,9 +109,72 @@ cbct_status done(hipError_t e)
 }  // namespace
 }  // namespace cbct
 
+// Partial sums of cbct_dot_noalloc: a fixed device array instead of a caller
+// workspace.  Each GPU holds its own copy for the life of the process; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the array's own name is not a device address on the
+// host).  Every call on one GPU shares it.
+static constexpr size_t kScratchCells = 1024;
+static __device__ __align__(256) double scratch[kScratchCells];
+static_assert(kScratchCells >= (size_t)cbct::kDotBlocks, "scratch holds every block's partial");
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices];   // per device, set on its first call
+
+// Device address of `scratch` on the current device, looked up once per device.
+cbct_status scratch_of_current_device(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        cbct::set_hip_error(e);
+        return CBCT_E_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices)
+        return CBCT_E_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            cbct::set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return CBCT_E_HIP;
+        }
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CBCT_OK;
+}
+
+}  // namespace
+
 using namespace cbct;
 
 extern "C" size_t cbct_dot_workspace(size_t) { return kDotBlocks; }
+
+extern "C" size_t cbct_dot_noalloc_max_cells(void) { return kScratchCells; }
+
+extern "C" cbct_status cbct_dot_noalloc(size_t n, const float *a, const float *b, double *out,
+                                        void *stream)
+{
+    if (!a || !b || !out)
+        return CBCT_E_NULL;
+    if (cbct_dot_workspace(n) > kScratchCells)
+        return CBCT_E_SHAPE;   // more partial sums than the fixed array holds
+    double *ws = nullptr;
+    const cbct_status st = scratch_of_current_device(&ws);
+    if (st != CBCT_OK)
+        return st;
+    // the same kernels as cbct_dot; dot_partial writes every cell it reads
+    // back, so nothing needs clearing
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(dot_partial, dim3(kDotBlocks), dim3(kT), 0, s, n, a, b, ws);
+    hipLaunchKernelGGL(dot_final, dim3(1), dim3(kT), 0, s, (const double *)ws, out);
+    return done(hipGetLastError());
+}
 
 extern "C" cbct_status cbct_dot(size_t n, const float *a, const float *b, double *ws, double *out,
                                 void *stream)
