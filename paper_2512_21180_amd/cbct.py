@@ -72,6 +72,9 @@ def _load():
     lib.cbct_philox_blocks.argtypes = [sz, u64, u32, vp, vp]
     lib.cbct_sim_poisson_log.argtypes = [sz, vp, vp, vp, dp, u64, u32, vp]
     lib.cbct_sim_gaussian.argtypes = [sz, vp, vp, dp, u64, u32, vp]
+    lib.cbct_water_bone.argtypes = [sz, vp, vp, vp, vp]
+    lib.cbct_poly_bins.argtypes = [i32, vp, vp, ctypes.POINTER(i32)]
+    lib.cbct_sim_poly.argtypes = [sz, sz, vp, vp, i32, vp, vp, vp, vp, u64, u32, vp, vp, vp, vp]
     fl = ctypes.c_float
     lib.cbct_pack16.argtypes = [sz, i32, ctypes.POINTER(vp), ctypes.POINTER(fl), vp, vp]
     lib.cbct_conv3.argtypes = [i32, i32, i32, vp, vp, i32, vp, vp, i32, fl, vp, i32,
@@ -382,6 +385,57 @@ def sim_poisson_log(p: torch.Tensor, I0: float, seed: int, stream_id: int = 0,
                                      float(I0), seed, stream_id, _stream(p.device)),
            "cbct_sim_poisson_log")
     return (out, c) if counts else out
+
+
+def water_bone(hu: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """[2, *hu.shape]: water and bone relative densities of a CT volume in HU
+    (channel 0 rho_w, channel 1 rho_b), ready for a two-channel forward."""
+    if out is None:
+        out = torch.empty((2,) + tuple(hu.shape), dtype=torch.float32, device=hu.device)
+    if out.shape[0] != 2 or out[0].numel() != hu.numel():
+        raise ValueError("out must be [2, *hu.shape]")
+    _check(_lib.cbct_water_bone(hu.numel(), _f32(hu, "hu"), _f32(out[0], "rho_w"),
+                                _f32(out[1], "rho_b"), _stream(hu.device)), "cbct_water_bone")
+    return out
+
+
+def poly_bins():
+    """(centres_keV, resp): the paper's ten energy bins and detector response."""
+    import numpy as np
+    c = np.zeros(32)
+    r = np.zeros(32)
+    n = ctypes.c_int32()
+    _check(_lib.cbct_poly_bins(32, c.ctypes.data_as(ctypes.c_void_p),
+                               r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)), "cbct_poly_bins")
+    return c[:n.value].copy(), r[:n.value].copy()
+
+
+def sim_poly(pw: torch.Tensor, pb: torch.Tensor, mu_w, mu_b, resp, I0: torch.Tensor, seed: int,
+             stream_id: int = 0, signal: bool = False, counts: bool = False):
+    """Noisy polychromatic primary signal and its normalised negative log
+    (cbct_sim_poly).  pw, pb: material line integrals (same shape, last two
+    dims the panel); I0: [n_bins, nv, nu] float32; mu_w, mu_b, resp: n_bins
+    host floats.  Returns y, plus the signal and/or the counts [n_bins, ...]
+    when asked."""
+    import numpy as np
+    if pw.shape != pb.shape:
+        raise ValueError("pw and pb differ in shape")
+    nb = I0.shape[0]
+    npix = I0[0].numel()
+    tabs = [np.ascontiguousarray(t, dtype=np.float64).ravel() for t in (mu_w, mu_b, resp)]
+    if any(t.size != nb for t in tabs):
+        raise ValueError("tables must have one entry per bin")
+    y = torch.empty_like(pw)
+    sg = torch.empty_like(pw) if signal else None
+    c = torch.empty((nb,) + tuple(pw.shape), dtype=torch.int64, device=pw.device) if counts else None
+    _check(_lib.cbct_sim_poly(pw.numel(), npix, _f32(pw, "pw"), _f32(pb, "pb"), nb,
+                              *[t.ctypes.data_as(ctypes.c_void_p) for t in tabs],
+                              _f32(I0, "I0"), seed, stream_id, _f32(y, "y"),
+                              ctypes.c_void_p(sg.data_ptr()) if sg is not None else None,
+                              ctypes.c_void_p(c.data_ptr()) if c is not None else None,
+                              _stream(pw.device)), "cbct_sim_poly")
+    out = (y,) + ((sg,) if signal else ()) + ((c,) if counts else ())
+    return out if len(out) > 1 else y
 
 
 def sim_gaussian(clean: torch.Tensor, sigma: float, seed: int, stream_id: int = 0,

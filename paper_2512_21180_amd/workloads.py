@@ -209,3 +209,46 @@ def phantom_c2_slab(g_slab: dict, seed: int, g_full: dict = None, n=50, body_dia
         e["centre"] = e["centre"] - np.array([0.0, 0.0, z0])
     body = dict(radius=0.5 * body_diameter, mu=0.02)
     return voxelise(g_slab, el, body=body)
+
+
+# ---- inputs of the polychromatic primary model (Sec. 2.2) ----
+#
+# The paper derives its intensity maps from a phase file of the scanner's
+# source and its material attenuation from published cross-section tables;
+# neither is available here.  The stand-ins below are synthetic: smooth
+# tables of the right magnitude and trend, not physical data.
+
+def hu_phantom(g: dict, seed: int, mu_water: float = 0.02) -> np.ndarray:
+    """A clinical-style phantom in Hounsfield units: the body cylinder
+    (300 mm, or 0.9 of the volume's width if smaller) at 0 HU (mu_water),
+    air at -1000 HU, and 50 additive ellipsoids of up to 2 mu_water each
+    (overlaps reach the bone range of the water-bone split)."""
+    rad = min(150.0, 0.45 * g["nx"] * g["vx"])
+    el = ellipsoid_list(g, seed, count=(50, 50), semi=(5.0, min(50.0, 0.4 * rad)),
+                        mu=(0.0, 2.0 * mu_water), body_radius=rad)
+    x = voxelise(g, el, body=dict(radius=rad, mu=mu_water))
+    return (1000.0 * (x / mu_water - 1.0)).astype(np.float32)
+
+
+def poly_tables(centres_kev) -> tuple:
+    """Synthetic attenuation per unit density (mm^-1) of water and bone at
+    the bin centres: a constant plus a photoelectric-like (25 keV / e)^3
+    term, larger for bone."""
+    e = np.asarray(centres_kev, dtype=np.float64)
+    pe = (25.0 / e) ** 3
+    return 0.017 + 0.033 * pe, 0.035 + 0.35 * pe
+
+
+def intensity_maps(g: dict, centres_kev, photons_per_mm2: float = 66000.0) -> np.ndarray:
+    """[n_bins, nv, nu] unattenuated photons per pixel and bin: photons per
+    mm^2 times the pixel area, split over the bins by a smooth spectrum
+    (peak near 55 keV) and shaped across the panel by a bow-tie-like fall-off
+    in the lateral (u) position."""
+    e = np.asarray(centres_kev, dtype=np.float64)
+    spec = np.exp(-0.5 * ((e - 55.0) / 22.0) ** 2)
+    spec /= spec.sum()
+    u = (np.arange(g["nu"]) - 0.5 * (g["nu"] - 1)) * g["du"] + g["off_u"]
+    bow = np.exp(-(u / 260.0) ** 2)
+    per_pix = photons_per_mm2 * g["du"] * g["dv"]
+    return (per_pix * spec[:, None, None] * bow[None, None, :] *
+            np.ones((1, g["nv"], 1))).astype(np.float32)

@@ -7,6 +7,8 @@ import math
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2512_21180_amd import workloads as W
@@ -111,3 +113,15 @@ def test_valid_geometry_passes_host_validation(cb):
         assert st in (0, -5), st
         if st == 0:
             assert cb.lib().cbct_geom_destroy(h) == 0
+
+
+def test_poly_bins_are_the_papers(cb, oracle):
+    """cbct_poly_bins (host only): the ten energy-bin centres and the
+    detector response at them, as the oracle defines them."""
+    c, r = cb.poly_bins()
+    assert c.tolist() == oracle.energy_bins().tolist()
+    np.testing.assert_allclose(r, oracle.detector_response(c), rtol=0, atol=1e-12)
+    n = ctypes.c_int32()
+    assert cb.lib().cbct_poly_bins(4, None, None, ctypes.byref(n)) == 0 and n.value == 10
+    buf = (ctypes.c_double * 4)()
+    assert cb.lib().cbct_poly_bins(4, buf, None, ctypes.byref(n)) == -4
