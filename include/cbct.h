@@ -132,7 +132,7 @@ cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,
  * vol = A^T sino for n_channels >= 1 stacked channels (layouts as above).
  * The weights are the ones cbct_forward applies, so the two are transposes
  * up to FP32 rounding of the sums.  Geometries whose panel windows exceed
- * 64 KB of LDS even for 8 x 8 x 4 voxel bricks run a one-thread-per-voxel
+ * 64 KB of LDS even for 8 x 7 x 4 voxel bricks run a one-thread-per-voxel
  * kernel with the same weights (slower).
  */
 cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
@@ -164,8 +164,8 @@ cbct_status cbct_geom_create_host(const cbct_geom_desc *desc, cbct_geom **out);
  * (float32 x 2); 3 forward tiles {angle, axis, u0, n_u, v0, n_v, p_lo, p_hi}
  * (int32 x 8); 4 the scalar block {n_angles, nu, nv, nx, ny, nz (int32), Kb,
  * vx, vy, vz, ox, oy, oz, sid, sdd, du, dv, off_u, off_v, cu, cv, rv0, rvs
- * (float32)}; 5 adjoint panel windows per angle and 8 x 8 brick column
- * ([n_angles][ceil(ny/8)][ceil(nx/8)], empty when the adjoint runs the
+ * (float32)}; 5 adjoint panel windows per angle and 8 x 7 brick column
+ * ([n_angles][ceil(ny/7)][ceil(nx/8)], empty when the adjoint runs the
  * one-thread-per-voxel kernel) {lambda_min, lambda_max (float32), u0 | u1 << 16,
  * row taps (int32)}. */
 cbct_status cbct_geom_table(const cbct_geom *g, int which, void *dst, size_t cap, size_t *bytes);
@@ -173,9 +173,10 @@ cbct_status cbct_geom_table(const cbct_geom *g, int which, void *dst, size_t cap
 /* Diagnostics: the launch plan chosen for a geometry.  Fills up to n of
  * {forward tiled (1/0), rays per thread, box in-plane, box z, tile count,
  *  adjoint bricked (1/0), window columns, window rows, LDS row stride,
- *  max row taps, voxels per adjoint thread along z (bricks are 8 x 8 x 4
- *  times that), forward tile columns (64 or 32)}.  A 0 in either flag means
- *  that operator runs the one-thread-per-output kernels. */
+ *  max row taps, voxels per adjoint thread along z (bricks are 4 times that
+ *  deep), forward tile columns (64 or 32), adjoint brick width along x,
+ *  adjoint brick width along y}.  A 0 in either flag means that operator
+ *  runs the one-thread-per-output kernels. */
 cbct_status cbct_geom_plan_info(const cbct_geom *g, int *info, int n);
 
 /* Static, human-readable description of a status code. */

@@ -44,9 +44,21 @@ def build_library(verbose: bool = False, jobs: int = 0) -> str:
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         return obj, _run([hipcc] + cflags + inc + ["-c", "-o", obj, src])
 
+    def stamps():
+        files = sources() + glob.glob(os.path.join(HERE, "csrc", "*.h")) + \
+            glob.glob(os.path.join(ROOT, "include", "*.h"))
+        return {f: os.stat(f).st_mtime_ns for f in files}
+
+    before = stamps()
     n = jobs or min(8, os.cpu_count() or 1)
     with ThreadPoolExecutor(max_workers=n) as ex:
         results = list(ex.map(compile_one, sources()))
+    # hipcc reads a source once for the device pass and again for the host
+    # pass: an edit during the build can pair one version's kernels with the
+    # other's launchers, so such a build is refused
+    changed = sorted(f for f, t in stamps().items() if before.get(f) != t)
+    if changed:
+        raise RuntimeError("sources changed during the build, rebuild: " + ", ".join(changed))
     tmp = LIB + ".tmp"
     msgs = [m for _, m in results] + [
         _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] +

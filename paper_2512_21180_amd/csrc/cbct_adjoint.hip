@@ -7,16 +7,28 @@
 // where p is the voxel's index along the ray's sampling axis and q_vox its
 // in-plane index; these are the weights the forward kernel applies.
 //
-// A workgroup owns a brick of 8 x 8 x 4 KV voxels (KV = 4, 2 or 1, chosen by
-// the plan so that the window fits in LDS); lane l of wave w owns the voxel
-// column (i0 + l%8, j0 + l/8) and the KV voxels k0 + KV w .. k0 + KV w + KV - 1,
-// and keeps their sums in registers over all angles (fixed order: angles,
-// then columns, then rows), so every voxel is written once and no atomics
-// are needed.  For each angle the brick's panel window is staged in LDS,
-// pre-multiplied by the ray length per plane ds, together with the column
-// constants; the window's columns, the source-panel scales that give its
-// rows and the row taps NT come from a table the host computes in FP64 per
-// angle and brick column.  Per voxel and column, the rows with non-zero weight lie above
+// A workgroup owns a brick of 8 x 7 x 4 KV output voxels (KV = 4, 2 or 1,
+// chosen by the plan so that the window fits in LDS); wave w owns the KV
+// voxel layers k0 + KV w .. k0 + KV w + KV - 1.  The in-plane weight of a
+// sample is shared by two voxels: a ray crossing the plane p at in-plane
+// index q lies in the segment [s, s + 1), s = floor(q), and weighs 1 - f on
+// voxel s and f on voxel s + 1 (f = q - s) with the same z weights.  So the
+// lanes own (plane, segment) pairs rather than voxels: on x planes lane l
+// takes plane i0 + l % 8 and segment j0 - 1 + l / 8 (eight segments feed
+// the seven output rows), on y planes lane l < 63 takes plane j0 + l / 9
+// and segment i0 - 1 + l % 9 (nine segments, eight output columns).  Each
+// column whose ray crosses the lane's plane in its segment (the test is the
+// forward's floor, so every column falls in exactly one segment) gets its
+// z run computed once and added with weight 1 - f and f to two register
+// sums; after the last angle the four shares of every output voxel (own and
+// lower segment, both axes) are added in a fixed order through LDS and
+// written once -- no atomics, and the order does not depend on timing.
+// Against one voxel per lane this halves the z runs per voxel.
+// For each angle the brick's panel window is staged in LDS, pre-multiplied
+// by the ray length per plane ds, together with the column constants; the
+// window's columns, the source-panel scales that give its rows and the row
+// taps NT come from a table the host computes in FP64 per angle and brick
+// column.  Per voxel and column, the rows with non-zero weight lie above
 // the row v_c where the ray crosses z = k - 1 and span less than 2 / beta
 // rows (beta: rows to z index, at least that of the brick's nearest point
 // to the source); the run of NT = floor(2 / beta) + 2 rows that starts at
@@ -39,17 +51,13 @@ namespace cbct {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kBI = 8, kBJ = 8;
-// One channel per window element (the gather is written for C channels per
-// element; a four-channel 8 x 8 x 4 variant measured 1.6x slower per channel
-// than the single-channel 8 x 8 x 16 bricks and was dropped).
 
 struct BrickArgs {
     DevGeom g;
     const BrickWin *wins;  // [n_angles][nby][nbx] panel windows
     int W, H, HS;          // window columns and rows, LDS column stride
     int nbx, nby, nbz;
-    int KV;                // voxels per thread along z (bricks 8 x 8 x 4 KV)
+    int KV;                // voxels per lane along z (bricks 8 x 7 x 4 KV)
 };
 
 __device__ inline float sat(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
@@ -66,37 +74,53 @@ __device__ inline void project_xy(const DevGeom &g, float inv_du, float c, float
     u = fmaf(fmaf(lam, fmaf(-s, x, c * y), -g.off_u), inv_du, g.cu);
 }
 
-// Inputs of one angle's gather for one thread (voxel column ic, jc and the
-// kV voxels from k0 up).
+// Inputs of one angle's gather for one lane.
 struct GatherIn {
     const DevGeom &g;
     const AngRec &ar;
     const float *yt;
     const float4 *cr;
-    int HS, U0, U1, V0, V1;
+    int HS, U0, U1, V0;
     int VS1;   // largest run start: max(V1 - NT + 1, V0), so a run ends in the window
-    int ic, jc, k0;
-    float cxv, cyv, inv_du, inv_rvs;
+    int k0;
+    int pl[2], sg[2];   // per sampling axis (0: x planes, 1: y planes): this lane's
+                        // plane and in-plane segment; pl < 0: no work on that axis
+    float inv_du, inv_rvs;
 };
 
-// Accumulate one angle's contributions into acc, reading NT taps per voxel
-// and column (rows past the non-zero run have zero weight).  The window holds
-// C channels per element; KV voxels per thread along z.
-// Both gather functions are forced inline: a call would impose the calling
+__device__ inline float centre_x(const DevGeom &g, float i)
+{
+    return g.ox + (i - 0.5f * (float)(g.nx - 1)) * g.vx;
+}
+
+__device__ inline float centre_y(const DevGeom &g, float j)
+{
+    return g.oy + (j - 0.5f * (float)(g.ny - 1)) * g.vy;
+}
+
+// Accumulate one angle's contributions of the columns whose rays cross this
+// lane's plane inside its segment [s, s + 1) of the in-plane index (the
+// forward's floor(q) = s): such a sample weighs 1 - f on in-plane voxel s and
+// f on voxel s + 1 (f = q - s), and the same z weights on both, so each
+// column's z run is computed once for the two voxels: lo[ax][n] collects the
+// 1 - f share (voxel s), hi[ax][n] the f share (voxel s + 1) for the KV
+// voxels k0 + n.  NT taps per voxel and column (rows past the non-zero run
+// have zero weight).  Forced inline: a call would impose the calling
 // convention's register budget and stack on the kernel.
-template <int NT, int C, int KV>
-__device__ __forceinline__ void gather_angle(const GatherIn &in, float (&acc)[KV][C])
+template <int NT, int KV>
+__device__ __forceinline__ void gather_angle(const GatherIn &in, float (&lo)[2][KV],
+                                             float (&hi)[2][KV])
 {
     const DevGeom &g = in.g;
     const AngRec &ar = in.ar;
-    const int HS = in.HS, U0 = in.U0, U1 = in.U1, V0 = in.V0, VS1 = in.VS1;
-    const int ic = in.ic, jc = in.jc, k0 = in.k0;
-    const float cxv = in.cxv, cyv = in.cyv, inv_du = in.inv_du, inv_rvs = in.inv_rvs;
+    const int HS = in.HS, U0 = in.U0, V0 = in.V0, VS1 = in.VS1;
+    const int k0 = in.k0;
+    const float inv_du = in.inv_du, inv_rvs = in.inv_rvs;
     const float *yt = in.yt;
     const float4 *cr = in.cr;
-    // Per voxel kk: the row where a ray with parameter t crosses z index
-    // kk - 1, plus 1/64, is Bk / t + A0; the hat argument at row r is
-    // t ((r - cv) rvs + rv0) + Kb - kk.
+    // Per voxel n: the row where a ray with parameter t crosses z index
+    // k0 + n - 1, plus 1/64, is Bk / t + A0; the hat argument at row r is
+    // t ((r - cv) rvs + rv0) + Kb - k.
     float Bk[KV], KbK[KV];
 #pragma unroll
     for (int n = 0; n < KV; ++n) {
@@ -106,55 +130,58 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&acc)[KV
     }
     const float A0 = fmaf(-g.rv0, inv_rvs, g.cv + 0.015625f);
     const float V0f = (float)V0, VS1f = (float)VS1;
+#pragma unroll
     for (int cls = 0; cls < 2; ++cls) {
-        int c_lo, c_hi;   // this axis' columns, intersected below
-        float fp, qv;
+        // this axis has columns at this angle (uniform) and this lane a segment
+        if (cls == 0 ? ar.x_lo >= ar.x_hi : (ar.x_lo == 0 && ar.x_hi == g.nu))
+            continue;
+        if (in.pl[cls] < 0)
+            continue;
+        const float fp = (float)in.pl[cls], sf = (float)in.sg[cls];
+        int c_lo, c_hi;   // this axis' columns
         float u1, u2, lam;
-        if (cls == 0) {   // x planes: plane i, in-plane j
-            if (ar.x_lo >= ar.x_hi)
-                continue;
+        if (cls == 0) {   // x planes: plane i, segment [s, s + 1) in y
             c_lo = ar.x_lo;
             c_hi = ar.x_hi - 1;
-            fp = (float)ic;
-            qv = (float)jc;
-            project_xy(g, inv_du, ar.c, ar.s, cxv, cyv - g.vy, u1, lam);
-            project_xy(g, inv_du, ar.c, ar.s, cxv, cyv + g.vy, u2, lam);
-        } else {          // y planes: plane j, in-plane i
-            if (ar.x_lo == 0 && ar.x_hi == g.nu)
-                continue;
+            const float xp = centre_x(g, fp), ya = centre_y(g, sf);
+            project_xy(g, inv_du, ar.c, ar.s, xp, ya, u1, lam);
+            project_xy(g, inv_du, ar.c, ar.s, xp, ya + g.vy, u2, lam);
+        } else {          // y planes: plane j, segment [s, s + 1) in x
             c_lo = 0;
             c_hi = g.nu - 1;
-            fp = (float)jc;
-            qv = (float)ic;
-            project_xy(g, inv_du, ar.c, ar.s, cxv - g.vx, cyv, u1, lam);
-            project_xy(g, inv_du, ar.c, ar.s, cxv + g.vx, cyv, u2, lam);
+            const float yp = centre_y(g, fp), xa = centre_x(g, sf);
+            project_xy(g, inv_du, ar.c, ar.s, xa, yp, u1, lam);
+            project_xy(g, inv_du, ar.c, ar.s, xa + g.vx, yp, u2, lam);
         }
+        // The segment's columns lie between the projections of its two
+        // edges (within rounding, far below a column): trim the candidate
+        // range's ends to columns that are members by the exact test (the
+        // membership test below keeps the partition exact in any case).
         int ul = max(max((int)floorf(fminf(u1, u2)), c_lo), U0);
-        int uh = min(min((int)ceilf(fmaxf(u1, u2)), c_hi), U1);
-        // The columns strictly between u1 and u2 have a non-zero in-plane
-        // weight; the floor and ceil columns usually have exactly zero
-        // weight: drop them when their own weight (computed as in the loop)
-        // is zero, so no non-zero term is ever skipped.
-        if (ul <= uh) {
-            const float4 cq = cr[ul - U0];
-            if (fabsf(fmaf(fp, cq.y, cq.x) - qv) >= 1.0f)
-                ++ul;
-        }
-        if (ul <= uh) {
-            const float4 cq = cr[uh - U0];
-            if (fabsf(fmaf(fp, cq.y, cq.x) - qv) >= 1.0f)
-                --uh;
-        }
+        int uh = min(min((int)ceilf(fmaxf(u1, u2)), c_hi), in.U1);
+        auto member = [&](int u) {
+            if (cls == 1 && u >= ar.x_lo && u < ar.x_hi)
+                return false;
+            const float4 cq = cr[u - U0];
+            const float f = fmaf(fp, cq.y, cq.x) - sf;
+            return f >= 0.0f && f < 1.0f;
+        };
+        while (ul <= uh && !member(ul))
+            ++ul;
+        while (uh > ul && !member(uh))
+            --uh;
         for (int u = ul; u <= uh; ++u) {
             if (cls == 1 && u >= ar.x_lo && u < ar.x_hi)
                 continue;   // those columns are sampled on x planes
             const float4 cq = cr[u - U0];
-            const float q = fmaf(fp, cq.y, cq.x);
-            const float wq = sat(1.0f - fabsf(q - qv));
+            const float f = fmaf(fp, cq.y, cq.x) - sf;
+            if (!(f >= 0.0f && f < 1.0f))
+                continue;   // the ray crosses this plane in another segment
+            const float wl = 1.0f - f;
             const float t = fmaf(fp, cq.w, cq.z);
             const float beta = t * g.rvs;
             const float rt = __builtin_amdgcn_rcpf(t);
-            const float *ycol = yt + ((u - U0) * HS - V0) * C;
+            const float *ycol = yt + (u - U0) * HS - V0;
 #pragma unroll
             for (int n = 0; n < KV; ++n) {
                 // run start, clamped into [V0, VS1] (a start moved down to
@@ -162,59 +189,58 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&acc)[KV
                 const float vsf =
                     __builtin_amdgcn_fmed3f(floorf(fmaf(rt, Bk[n], A0)), V0f, VS1f);
                 float s = fmaf(t, fmaf(vsf - g.cv, g.rvs, g.rv0), KbK[n]);
-                const float *py = ycol + (int)vsf * C;
-                float csum[C];
+                const float *py = ycol + (int)vsf;
+                float yv[NT];
 #pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    csum[ch] = 0.0f;
-                float yv[NT * C];
-#pragma unroll
-                for (int m = 0; m < NT * C; ++m)
+                for (int m = 0; m < NT; ++m)
                     yv[m] = py[m];
+                float csum = 0.0f;
 #pragma unroll
                 for (int m = 0; m < NT; ++m) {
-                    const float wz = sat(1.0f - fabsf(s));
-#pragma unroll
-                    for (int ch = 0; ch < C; ++ch)
-                        csum[ch] = fmaf(wz, yv[m * C + ch], csum[ch]);
+                    csum = fmaf(sat(1.0f - fabsf(s)), yv[m], csum);
                     s += beta;
                 }
-#pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    acc[n][ch] = fmaf(wq, csum[ch], acc[n][ch]);
+                lo[cls][n] = fmaf(wl, csum, lo[cls][n]);
+                hi[cls][n] = fmaf(f, csum, hi[cls][n]);
             }
         }
     }
 }
 
-// Gather one brick (index b) for C channels (the first nch of them live):
-// ys[c] is channel c's sinogram, vols[c] its volume.  Bricks are 8 x 8 x 4 KV
-// voxels; thread (lane, wave w) owns voxel column (lane % 8, lane / 8) and
-// the KV voxels from 4 KV (brick z) + KV w up.  `lds` holds the panel window,
-// column-major with C channels per element ([W][HS][C], HS = 2 mod 4, which
-// suits the gather's reads), and the column table.
-template <class SS, class VS, int C, int KV>
+// Gather one brick (index b): bricks hold kAdjBI x kAdjBJ x 4 KV output
+// voxels.  Lane roles (wave w owns the KV voxel layers from 4 KV (brick z) +
+// KV w up): on x planes lane l takes plane i0 + l % 8 and in-plane segment
+// j0 - 1 + l / 8 (eight segments serve the seven output rows j0 .. j0 + 6);
+// on y planes lane l < 63 takes plane j0 + l / 9 and segment i0 - 1 + l % 9
+// (nine segments serve the eight output columns).  After the last angle the
+// four shares each output voxel receives (lo of its own segment and hi of
+// the one below, on each axis) are added in a fixed order through LDS.
+// `lds` holds the panel window, column-major ([W][HS], HS = 2 mod 4, which
+// suits the gather's reads), and the column table; then the exchange.
+template <class SS, class VS, int KV>
 __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
-                                             const typename SS::T *const (&ys)[C],
-                                             typename VS::T *const (&vols)[C], int nch,
-                                             float *lds)
+                                             const typename SS::T *ys,
+                                             typename VS::T *vol, float *lds)
 {
     constexpr int kBK = 4 * KV;
-    constexpr int kSB = C == 1 ? 8 : 4;   // rows per staging batch (loads in flight)
+    constexpr int kSB = 8;   // rows per staging batch (loads in flight)
     const DevGeom &g = A.g;
     const int HS = A.HS;
-    float *yt = lds;                                        // ds-weighted panel window
-    float4 *cr = (float4 *)(lds + (size_t)A.W * HS * C);    // [W] (pb, ps, t0, tau)
+    float *yt = lds;                                    // ds-weighted panel window
+    float4 *cr = (float4 *)(lds + (size_t)A.W * HS);    // [W] (pb, ps, t0, tau)
 
     const int bx = b % A.nbx, by = (b / A.nbx) % A.nby, bz = b / (A.nbx * A.nby);
 
     // the wave index is uniform (scalar registers for its row and layer indices)
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int i = bx * kBI + (lane & 7), j = by * kBJ + (lane >> 3);
+    const int i0 = bx * kAdjBI, j0 = by * kAdjBJ;
     const int k0 = bz * kBK + w * KV;
-    const int ic = min(i, g.nx - 1), jc = min(j, g.ny - 1);
-    const float cxv = g.ox + ((float)ic - 0.5f * (float)(g.nx - 1)) * g.vx;
-    const float cyv = g.oy + ((float)jc - 0.5f * (float)(g.ny - 1)) * g.vy;
+    int pl0 = i0 + (lane & 7), sg0 = j0 - 1 + (lane >> 3);
+    int pl1 = j0 + lane / 9, sg1 = i0 - 1 + lane % 9;
+    if (pl0 >= g.nx || sg0 >= g.ny)
+        pl0 = -1;
+    if (lane >= 63 || pl1 >= g.ny || sg1 >= g.nx)
+        pl1 = -1;
 
     // z extent of the brick's support (voxel centres +- one pitch), uniform
     const int kz0 = bz * kBK, kz1 = min(kz0 + kBK, g.nz) - 1;
@@ -228,12 +254,14 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
     // z of this wave's first voxel layer (wave-uniform)
     const float zc_w0 = g.oz + ((float)k0 - 0.5f * (float)(g.nz - 1)) * g.vz;
     const float inv_rvs = 1.0f / g.rvs;
-    float acc[KV][C];
+    float lo[2][KV], hi[2][KV];
 #pragma unroll
-    for (int n = 0; n < KV; ++n)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-            acc[n][ch] = 0.0f;
+        for (int n = 0; n < KV; ++n) {
+            lo[c][n] = 0.0f;
+            hi[c][n] = 0.0f;
+        }
 
     __syncthreads();   // the previous work item's readers of lds are done
     for (int a = 0; a < g.n_angles; ++a) {
@@ -271,12 +299,12 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
             // 32-bit offsets within this projection (nv nu < 2^24 words)
             const size_t pa = (size_t)a * g.nv * g.nu;
             const int u = U0 + uu;
-            float *dst = yt + (size_t)uu * HS * C;
+            float *dst = yt + (size_t)uu * HS;
             for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
                 // Raw stored values, widened at the LDS store.  Rows past V1
                 // (stored as zeros) load row V1 instead, so no load sits
                 // behind a branch that would make it wait for its value.
-                typename SS::Raw val[kSB][C];
+                typename SS::Raw val[kSB];
                 float vsq[kSB];
                 bool live[kSB];
 #pragma unroll
@@ -285,10 +313,7 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
                     live[jj] = v <= V1;
                     const int vr = min(v, V1);
                     const size_t off = pa + (size_t)(__mul24(vr, g.nu) + u);
-#pragma unroll
-                    for (int ch = 0; ch < C; ++ch)
-                        val[jj][ch] = (C == 1 || ch < nch) ? SS::raw(ys[ch], off)
-                                                           : typename SS::Raw(0);
+                    val[jj] = SS::raw(ys, off);
                     vsq[jj] = g.rows[vr].y;
                 }
 #pragma unroll
@@ -296,18 +321,7 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
                     const int vv = vv0 + 4 * jj;
                     if (vv < Hs) {
                         const float ds = ray_ds(col.dsf, col.n2, vsq[jj]);
-                        float out[C];
-#pragma unroll
-                        for (int ch = 0; ch < C; ++ch)
-                            out[ch] = live[jj] ? SS::wide(val[jj][ch]) * ds : 0.0f;
-                        if constexpr (C == 4) {
-                            *reinterpret_cast<float4 *>(dst + (size_t)vv * 4) =
-                                make_float4(out[0], out[1], out[2], out[3]);
-                        } else {
-#pragma unroll
-                            for (int ch = 0; ch < C; ++ch)
-                                dst[(size_t)vv * C + ch] = out[ch];
-                        }
+                        dst[vv] = live[jj] ? SS::wide(val[jj]) * ds : 0.0f;
                     }
                 }
             }
@@ -328,39 +342,55 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
         }
         // ---- gather with a compile-time tap count (NT rounded up to a
         // supported count; extra taps read zero weight)
-        const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, V1, VS1, ic, jc, k0, cxv, cyv, inv_du,
-                          inv_rvs};
+        const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, VS1, k0, {pl0, pl1}, {sg0, sg1},
+                          inv_du, inv_rvs};
         switch (NT) {
-        case 4: gather_angle<4, C, KV>(in, acc); break;
-        case 5: gather_angle<5, C, KV>(in, acc); break;
-        case 6: gather_angle<6, C, KV>(in, acc); break;
-        case 7: gather_angle<7, C, KV>(in, acc); break;
-        case 8: gather_angle<8, C, KV>(in, acc); break;
-        case 9: gather_angle<9, C, KV>(in, acc); break;
-        case 10: gather_angle<10, C, KV>(in, acc); break;
-        case 11: gather_angle<11, C, KV>(in, acc); break;
-        case 12: gather_angle<12, C, KV>(in, acc); break;
-        case 13: gather_angle<13, C, KV>(in, acc); break;
-        case 14: gather_angle<14, C, KV>(in, acc); break;
-        case 15: gather_angle<15, C, KV>(in, acc); break;
-        case 16: gather_angle<16, C, KV>(in, acc); break;
-        case 18: gather_angle<18, C, KV>(in, acc); break;
-        case 20: gather_angle<20, C, KV>(in, acc); break;
-        case 24: gather_angle<24, C, KV>(in, acc); break;
-        case 28: gather_angle<28, C, KV>(in, acc); break;
-        default: gather_angle<32, C, KV>(in, acc); break;
+        case 4: gather_angle<4, KV>(in, lo, hi); break;
+        case 5: gather_angle<5, KV>(in, lo, hi); break;
+        case 6: gather_angle<6, KV>(in, lo, hi); break;
+        case 7: gather_angle<7, KV>(in, lo, hi); break;
+        case 8: gather_angle<8, KV>(in, lo, hi); break;
+        case 9: gather_angle<9, KV>(in, lo, hi); break;
+        case 10: gather_angle<10, KV>(in, lo, hi); break;
+        case 11: gather_angle<11, KV>(in, lo, hi); break;
+        case 12: gather_angle<12, KV>(in, lo, hi); break;
+        case 13: gather_angle<13, KV>(in, lo, hi); break;
+        case 14: gather_angle<14, KV>(in, lo, hi); break;
+        case 15: gather_angle<15, KV>(in, lo, hi); break;
+        case 16: gather_angle<16, KV>(in, lo, hi); break;
+        case 18: gather_angle<18, KV>(in, lo, hi); break;
+        case 20: gather_angle<20, KV>(in, lo, hi); break;
+        case 24: gather_angle<24, KV>(in, lo, hi); break;
+        case 28: gather_angle<28, KV>(in, lo, hi); break;
+        default: gather_angle<32, KV>(in, lo, hi); break;
         }
     }
 
-    if (i < g.nx && j < g.ny) {
+    // ---- each output voxel's four shares, added in a fixed order: x planes
+    // (lo of its own segment, hi of the segment below), then y planes (same)
+    __syncthreads();   // every wave is done with the window
+    float *xch = lds + (size_t)w * (4 * 64 * KV);
+#pragma unroll
+    for (int n = 0; n < KV; ++n) {
+        xch[(0 * KV + n) * 64 + lane] = lo[0][n];
+        xch[(1 * KV + n) * 64 + lane] = hi[0][n];
+        xch[(2 * KV + n) * 64 + lane] = lo[1][n];
+        xch[(3 * KV + n) * 64 + lane] = hi[1][n];
+    }
+    __syncthreads();
+    const int io = lane & 7, jo = lane >> 3;
+    const int i = i0 + io, j = j0 + jo;
+    if (jo < kAdjBJ && i < g.nx && j < g.ny) {
+        const int xl = ((jo + 1) << 3) | io, xh = (jo << 3) | io;   // x-plane lanes
+        const int yl = jo * 9 + io + 1, yh = jo * 9 + io;           // y-plane lanes
 #pragma unroll
         for (int n = 0; n < KV; ++n) {
             const int k = k0 + n;
             if (k < g.nz) {
-#pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    if (C == 1 || ch < nch)
-                        VS::st(vols[ch], ((size_t)k * g.ny + j) * g.nx + i, acc[n][ch]);
+                float v = xch[(0 * KV + n) * 64 + xl] + xch[(1 * KV + n) * 64 + xh];
+                v += xch[(2 * KV + n) * 64 + yl];
+                v += xch[(3 * KV + n) * 64 + yh];
+                VS::st(vol, ((size_t)k * g.ny + j) * g.nx + i, v);
             }
         }
     }
@@ -401,9 +431,7 @@ adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
-    const typename SS::T *ys[1] = {sino + ch * nsino};
-    typename VS::T *vs[1] = {vol + ch * nvox};
-    gather_brick<SS, VS, 1, KV>(A, b, ys, vs, 1, lds);
+    gather_brick<SS, VS, KV>(A, b, sino + ch * nsino, vol + ch * nvox, lds);
 }
 
 // ---- batched adjoint: one launch over all (case, brick) items ---------------
@@ -435,12 +463,12 @@ adjoint_batch(BatchAdjArgs B)
     const int b = brick_of_slot(C.A, xc, li - B.first[cs]);
     if (b < 0)
         return;
-    const typename SS::T *ys[1] = {(const typename SS::T *)C.sino};
-    typename VS::T *vs[1] = {(typename VS::T *)C.vol};
+    const auto *ys = (const typename SS::T *)C.sino;
+    auto *vs = (typename VS::T *)C.vol;
     switch (C.A.KV) {   // uniform over the workgroup
-    case 4: gather_brick<SS, VS, 1, 4>(C.A, b, ys, vs, 1, lds); break;
-    case 2: gather_brick<SS, VS, 1, 2>(C.A, b, ys, vs, 1, lds); break;
-    default: gather_brick<SS, VS, 1, 1>(C.A, b, ys, vs, 1, lds); break;
+    case 4: gather_brick<SS, VS, 4>(C.A, b, ys, vs, lds); break;
+    case 2: gather_brick<SS, VS, 2>(C.A, b, ys, vs, lds); break;
+    default: gather_brick<SS, VS, 1>(C.A, b, ys, vs, lds); break;
     }
 }
 
@@ -449,13 +477,17 @@ adjoint_batch(BatchAdjArgs B)
 static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
 {
     const int bk = 4 * p.KV;
-    return BrickArgs{g, p.wins, p.W, p.H, p.WS, (g.nx + kBI - 1) / kBI,
-                     (g.ny + kBJ - 1) / kBJ, (g.nz + bk - 1) / bk, p.KV};   // WS: column stride
+    return BrickArgs{g, p.wins, p.W, p.H, p.WS, (g.nx + kAdjBI - 1) / kAdjBI,
+                     (g.ny + kAdjBJ - 1) / kAdjBJ, (g.nz + bk - 1) / bk, p.KV};   // WS: column stride
 }
 
-static size_t brick_lds(const AdjPlan &p, int channels)
+// The window and column table, or the final exchange (four shares per lane
+// and voxel layer, four waves) if that is larger.
+static size_t brick_lds(const AdjPlan &p)
 {
-    return ((size_t)p.W * p.WS * channels + (size_t)p.W * 4) * sizeof(float);
+    const size_t window = (size_t)p.W * p.WS + (size_t)p.W * 4;
+    const size_t exchange = (size_t)4 * 4 * 64 * p.KV;
+    return std::max(window, exchange) * sizeof(float);
 }
 
 hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *sino,
@@ -467,7 +499,7 @@ hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
-        const size_t lds = brick_lds(p, 1);
+        const size_t lds = brick_lds(p);
         const auto *y = (const typename SS::T *)sino;
         auto *x = (typename VS::T *)vol;
         if (p.KV == 4)
@@ -492,7 +524,7 @@ hipError_t launch_adjoint_batch(int n, const cbct_geom *const *gs, const void *c
         B.first[i] = items;
         B.c[i] = AdjCase{brick_args(g->dev, g->adj), sinos[i], vols[i]};
         items += slots_per_xcd(B.c[i].A);
-        lds = std::max(lds, brick_lds(g->adj, 1));
+        lds = std::max(lds, brick_lds(g->adj));
     }
     B.first[n] = items;
     B.n_items = items;

@@ -179,10 +179,10 @@ extern "C" cbct_status cbct_geom_plan_info(const cbct_geom *g, int *info, int n)
 {
     if (!g || !info)
         return CBCT_E_NULL;
-    int v[12] = {g->fwd.ok ? 1 : 0, g->fwd.R,  g->fwd.BQ, g->fwd.BK,    g->fwd.n_tiles,
+    int v[14] = {g->fwd.ok ? 1 : 0, g->fwd.R,  g->fwd.BQ, g->fwd.BK,    g->fwd.n_tiles,
                  g->adj.ok ? 1 : 0, g->adj.W,  g->adj.H,  g->adj.WS,    g->adj.NTmax,
-                 g->adj.KV,         g->fwd.TU};
-    for (int i = 0; i < n && i < 12; ++i)
+                 g->adj.KV,         g->fwd.TU, kAdjBI,    kAdjBJ};
+    for (int i = 0; i < n && i < 14; ++i)
         info[i] = v[i];
     return CBCT_OK;
 }

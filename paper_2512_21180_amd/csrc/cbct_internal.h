@@ -87,10 +87,16 @@ __host__ __device__ inline int adj_taps_rounded(int nt)
     return 32;
 }
 
-// Adjoint plan: bricks of 8 x 8 x 16 voxels; per angle the brick's panel
+// Adjoint bricks: kAdjBI x kAdjBJ output voxel columns (x, y) and 4 KV
+// voxels along z.  One wave's 64 lanes serve the brick's in-plane segments
+// on either sampling axis: 8 planes x 8 segments on x planes (seven output
+// rows need eight segments), 7 planes x 9 segments on y planes.
+constexpr int kAdjBI = 8, kAdjBJ = 7;
+
+// Adjoint plan: per angle the brick's panel
 // footprint (at most W x H pixels, clipped to the panel) is staged in LDS.
-// Panel window of one adjoint brick column (8 x 8 voxels, all z) at one
-// angle, from the FP64 projections of its support box (voxel centres +- one
+// Panel window of one adjoint brick column (kAdjBI x kAdjBJ voxels, all z)
+// at one angle, from the FP64 projections of its support box (voxel centres +- one
 // pitch): columns [u0, u1] (u0 > u1: the column is not seen), the extreme
 // source-panel scales (a point at height z lands at V = lambda z) and the
 // row taps per voxel and column its rays need.
@@ -106,7 +112,7 @@ struct AdjPlan {
     int W = 0, H = 0;  // footprint bounds (columns, rows)
     int WS = 0;        // LDS column stride of the window (floats, 2 mod 4)
     int NTmax = 0;     // largest row-tap count
-    int KV = 4;        // voxels per thread along z: bricks are 8 x 8 x 4 KV
+    int KV = 4;        // voxels per thread along z: bricks are kAdjBI x kAdjBJ x 4 KV
     const BrickWin *wins = nullptr;   // device: [n_angles][nby][nbx]
 };
 

@@ -12,7 +12,7 @@
 // times 8, 4, 2, 1 rows whose boxes fit.  Volumes of 4 GiB or more (the
 // kernel's offsets are 32-bit) take the one-thread-per-ray kernel.
 //
-// Adjoint: the volume is cut into 8 x 8 x 4 KV bricks (KV = 4, 2 or 1 voxels
+// Adjoint: the volume is cut into 8 x 7 x 4 KV bricks (KV = 4, 2 or 1 voxels
 // per thread along z).  For every angle a brick's support (voxel centres +-
 // one pitch) projects onto the panel inside a W x H window that is staged in
 // LDS; W and H are the largest windows over all bricks and angles.  Each
@@ -36,7 +36,7 @@ namespace {
 
 constexpr int kMaxBoxQ = 64;      // staged box: one 64-lane row per z index
 constexpr int kMaxBoxK = 32;      // and at most 32 rows
-constexpr int kBI = 8, kBJ = 8;
+constexpr int kBI = kAdjBI, kBJ = kAdjBJ;
 constexpr size_t kAdjLdsShare = 40 * 1024;    // four workgroups per CU
 constexpr size_t kAdjLdsBudget = 64 * 1024;
 constexpr long kMinBricks = 2 * 256;          // two bricks per CU
@@ -119,7 +119,7 @@ TileBuild make_tiles(const cbct_geom *g, int TU, int TV)
     return tb;
 }
 
-// Panel windows of every brick column (8 x 8 voxels, all z) at every angle,
+// Panel windows of every brick column (8 x 7 voxels, all z) at every angle,
 // in FP64: the projections of the support box corners (voxel centres +- one
 // pitch) give the column range (one column of margin on each side, clipped
 // to the panel), the extreme source-panel scales and the smallest ray
@@ -187,7 +187,7 @@ WinTable brick_windows(const cbct_geom *g, int NTmax)
     return t;
 }
 
-// Window bounds of bricks 8 x 8 x bk staging `channels` channels per
+// Window bounds of bricks 8 x 7 x bk staging `channels` channels per
 // element; ok when the window fits the LDS budget.  Per brick layer the row
 // range follows from the brick column's scales (rows are linear in z for a
 // fixed scale), clipped to the panel as the kernel clips it, with the

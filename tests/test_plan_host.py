@@ -64,7 +64,10 @@ class Host:
         self.rows = self.table(2, np.float32).reshape(g["nv"], 2)
         self.tiles = self.table(3, np.int32).reshape(-1, 8)
         wins = self.table(5, np.uint8)
-        nbx, nby = -(-g["nx"] // 8), -(-g["ny"] // 8)
+        info = (ctypes.c_int * 14)()
+        lib.cbct_geom_plan_info(h, info, 14)
+        self.info = list(info)
+        nbx, nby = -(-g["nx"] // self.info[12]), -(-g["ny"] // self.info[13])
         self.win_l = wins.view(np.float32).reshape(g["n_angles"], nby, nbx, 4)[..., :2] \
             if wins.size else None
         self.win_i = wins.view(np.uint32).reshape(g["n_angles"], nby, nbx, 4)[..., 2:] \
@@ -75,9 +78,6 @@ class Host:
         names = ["Kb", "vx", "vy", "vz", "ox", "oy", "oz", "sid", "sdd", "du", "dv", "off_u",
                  "off_v", "cu", "cv", "rv0", "rvs"]
         self.s = dict(zip(names, fl[:len(names)]))
-        info = (ctypes.c_int * 12)()
-        lib.cbct_geom_plan_info(h, info, 12)
-        self.info = list(info)
 
     def table(self, which, dtype):
         n = ctypes.c_size_t()
@@ -213,8 +213,9 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
     nx, ny, nz, nu, nv = g["nx"], g["ny"], g["nz"], g["nu"], g["nv"]
     W_, H_, WS, NTmax = _adj_plan(h, bk)
     Kb, rvs, rv0, cv = s["Kb"], s["rvs"], s["rv0"], s["cv"]
-    i0, i1 = bx * 8, min(bx * 8 + 8, nx) - 1
-    j0, j1 = by * 8, min(by * 8 + 8, ny) - 1
+    BI, BJ = h.info[12], h.info[13]
+    i0, i1 = bx * BI, min(bx * BI + BI, nx) - 1
+    j0, j1 = by * BJ, min(by * BJ + BJ, ny) - 1
     k0, k1 = bz * bk, min(bz * bk + bk, nz) - 1
 
     def cx(i):
@@ -259,47 +260,72 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
         Hs = max(V1 - V0 + 1, NT)
         VS1 = max(V1 - NT + 1, V0)
         assert U1 - U0 + 1 <= W_ and Hs <= H_ and H_ <= WS and WS % 4 == 2
+        # lane roles: on x planes, plane i and in-plane segment [s, s + 1) of y
+        # for s = j0 - 1 .. j0 + BJ - 1; on y planes, plane j and segment of x
+        # for s = i0 - 1 .. i0 + BI - 1
+        roles = []
+        if x_lo < x_hi:
+            for i in range(i0, min(i0 + BI, nx)):
+                for sg in range(j0 - 1, min(j0 + BJ, ny)):
+                    roles.append((0, i, sg))
+        if not (x_lo == 0 and x_hi == nu):
+            for j in range(j0, min(j0 + BJ, ny)):
+                for sg in range(i0 - 1, min(i0 + BI, nx)):
+                    roles.append((1, j, sg))
+        for cls, pl, sg in roles:
+            fp, sf = f32(pl), f32(sg)
+            if cls == 0:
+                lo_c, hi_c = x_lo, x_hi - 1
+                u1, _ = proj(c_, s_, cx(pl), cy(sg))
+                u2, _ = proj(c_, s_, cx(pl), f32(cy(sg) + s["vy"]))
+                cols_ok = np.arange(x_lo, x_hi)
+            else:
+                lo_c, hi_c = 0, nu - 1
+                u1, _ = proj(c_, s_, cx(sg), cy(pl))
+                u2, _ = proj(c_, s_, f32(cx(sg) + s["vx"]), cy(pl))
+                cols_ok = np.setdiff1d(np.arange(nu), np.arange(x_lo, x_hi))
+            ul = max(max(int(np.floor(min(u1, u2))), lo_c), U0)
+            uh = min(min(int(np.ceil(max(u1, u2))), hi_c), U1)
+            # the segment's members, as the forward floors the in-plane index
+            C = h.cols[a, cols_ok]
+            q = fma32(fp, C[:, 1], C[:, 0])
+            f = (q - sf).astype(np.float32)
+            mem = cols_ok[(f >= 0) & (f < 1)]
+            assert np.all((mem >= ul) & (mem <= uh)), (a, cls, pl, sg, mem, ul, uh)
+            # the candidates between two members are members too (the kernel
+            # trims only the ends; a column inside is tested again anyway)
+            for u in mem:
+                Cu = h.cols[a, u]
+                t = fma32(fp, Cu[3], Cu[2])
+                rt = f32(1.0) / t
+                Vz = h.rows[:, 0]
+                kf = fma32(fp, (Cu[3] * Vz).astype(np.float32), fma32(Cu[2], Vz, Kb))
+                for kk in range(k0, k1 + 1):
+                    rows_sup = np.nonzero(np.abs(kf.astype(np.float64) - kk) < 1.0)[0]
+                    inv_rvs = f32(f32(1.0) / rvs)
+                    Bk = f32(f32(f32(f32(kk) - f32(1.0)) - Kb) * inv_rvs)
+                    A0 = fma32(-rv0, inv_rvs, f32(cv + f32(0.015625)))
+                    vf = fma32(rt, Bk, A0)
+                    vstart = min(max(int(np.floor(vf)), V0), VS1)
+                    assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)
+                                  & (rows_sup <= V1)), \
+                        (a, cls, pl, sg, kk, u, rows_sup, vstart, NT, V1)
+                    checked += len(rows_sup)
+        # every non-zero in-plane weight of an output voxel comes from one of
+        # the lanes' segments (the voxel's own or the one below)
         for i in range(i0, i1 + 1):
             for j in range(j0, j1 + 1):
-                for cls in (0, 1):
-                    if cls == 0:
-                        if x_lo >= x_hi:
-                            continue
-                        lo_c, hi_c, fp, qv = x_lo, x_hi - 1, f32(i), f32(j)
-                        u1, _ = proj(c_, s_, cx(i), f32(cy(j) - s["vy"]))
-                        u2, _ = proj(c_, s_, cx(i), f32(cy(j) + s["vy"]))
-                        cols_ok = np.arange(x_lo, x_hi)
-                    else:
-                        if x_lo == 0 and x_hi == nu:
-                            continue
-                        lo_c, hi_c, fp, qv = 0, nu - 1, f32(j), f32(i)
-                        u1, _ = proj(c_, s_, f32(cx(i) - s["vx"]), cy(j))
-                        u2, _ = proj(c_, s_, f32(cx(i) + s["vx"]), cy(j))
-                        cols_ok = np.setdiff1d(np.arange(nu), np.arange(x_lo, x_hi))
-                    ul = max(max(int(np.floor(min(u1, u2))), lo_c), U0)
-                    uh = min(min(int(np.ceil(max(u1, u2))), hi_c), U1)
-                    # true in-plane support, as the forward kernel weighs it
+                for cls, fp, qv, ok in ((0, i, j, x_lo < x_hi),
+                                        (1, j, i, not (x_lo == 0 and x_hi == nu))):
+                    if not ok:
+                        continue
+                    cols_ok = np.arange(x_lo, x_hi) if cls == 0 else \
+                        np.setdiff1d(np.arange(nu), np.arange(x_lo, x_hi))
                     C = h.cols[a, cols_ok]
-                    q = fma32(fp, C[:, 1], C[:, 0])
-                    sup = cols_ok[np.abs(q.astype(np.float64) - qv) < 1.0]
-                    assert np.all((sup >= ul) & (sup <= uh)), (a, i, j, cls, sup, ul, uh)
-                    for u in sup:
-                        Cu = h.cols[a, u]
-                        t = fma32(fp, Cu[3], Cu[2])
-                        rt = f32(1.0) / t
-                        Vz = h.rows[:, 0]
-                        kf = fma32(fp, (Cu[3] * Vz).astype(np.float32), fma32(Cu[2], Vz, Kb))
-                        for kk in range(k0, k1 + 1):
-                            rows_sup = np.nonzero(np.abs(kf.astype(np.float64) - kk) < 1.0)[0]
-                            inv_rvs = f32(f32(1.0) / rvs)
-                            Bk = f32(f32(f32(f32(kk) - f32(1.0)) - Kb) * inv_rvs)
-                            A0 = fma32(-rv0, inv_rvs, f32(cv + f32(0.015625)))
-                            vf = fma32(rt, Bk, A0)
-                            vstart = min(max(int(np.floor(vf)), V0), VS1)
-                            assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)
-                                          & (rows_sup <= V1)), \
-                                (a, i, j, kk, u, rows_sup, vstart, NT, V1)
-                            checked += len(rows_sup)
+                    q = fma32(f32(fp), C[:, 1], C[:, 0])
+                    segs = np.floor(q[np.abs(q.astype(np.float64) - qv) < 1.0]).astype(int)
+                    lane_segs = {r[2] for r in roles if r[0] == cls and r[1] == fp}
+                    assert set(segs.tolist()) <= lane_segs, (a, cls, i, j, set(segs), lane_segs)
     return checked
 
 
@@ -308,7 +334,8 @@ def test_adjoint_windows_cover_every_weight(hosts, name):
     h = hosts[name]
     g = GEOMS[name]
     assert h.info[5] == 1, "bricked adjoint expected"
-    nbx, nby = -(-g["nx"] // 8), -(-g["ny"] // 8)
+    assert (h.info[12], h.info[13]) == (8, 7)
+    nbx, nby = -(-g["nx"] // h.info[12]), -(-g["ny"] // h.info[13])
     rng = W.rng(5)
     n_b = 3 if name in ("c2", "c4") else 6
     na = g["n_angles"]
