@@ -94,7 +94,7 @@ def record_traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
     import csv
 
     def per_kernel(path, counter):
-        out = {}
+        out, copies = {}, []
         with open(path) as f:
             for r in csv.DictReader(f):
                 if r["Counter_Name"] != counter:
@@ -103,10 +103,13 @@ def record_traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
                 key = ("copy" if "copyBuffer" in name else
                        "adjoint" if "adjoint_brick" in name else
                        "forward" if "forward_sweep" in name else None)
-                if key == "copy" and int(r["Grid_Size"]) < 4096:
-                    continue            # small staging copies, not the calibration copy
-                if key:
+                if key == "copy":
+                    if int(r["Grid_Size"]) >= 4096:   # not the small staging copies
+                        copies.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+                elif key:
                     out.setdefault(key, []).append(float(r["Counter_Value"]))
+        # the calibration copies are the run's last two large copies
+        out["copy"] = [v for _, v in sorted(copies)[-2:]]
         return out
 
     fe, wr = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
@@ -560,7 +563,10 @@ def main():
             "traffic": measured_traffic(dom),
             "algorithmic_bytes": algorithmic_bytes(g),
         },
-        "gather_bound": gather_bound(S, 4, tA, tAT, copy_bandwidth()),
+        # (counter runs with --copy-calibration leave out the bandwidth copies,
+        # so that the calibration copies are the only large ones)
+        "gather_bound": None if args.copy_calibration else
+        gather_bound(S, 4, tA, tAT, copy_bandwidth()),
     }
     if args.copy_calibration:
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")

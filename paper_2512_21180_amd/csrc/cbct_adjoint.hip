@@ -31,10 +31,14 @@
 // column.  Per voxel and column, the rows with non-zero weight lie above
 // the row v_c where the ray crosses z = k - 1 and span less than 2 / beta
 // rows (beta: rows to z index, at least that of the brick's nearest point
-// to the source); the run of NT = floor(2 / beta) + 2 rows that starts at
-// floor(v_c + 1/64) holds them all (the 1/64 row exceeds the rounding of
-// v_c many times, so the start is floor(v_c) or, when v_c lies within 1/64
-// below an integer, that integer, and every row below it has zero weight).
+// to the source); the run of NT = floor(2 / beta) + 1 rows that starts at
+// floor(v_c) + 1, the first row above v_c, holds them all.  The start is
+// taken as floor(v_c + 1 - delta), delta a few times the FP32 rounding of v_c
+// (adj_start_delta): it is the first row above v_c, or one row lower when
+// v_c lies within 2 delta above an integer -- a row of zero weight, and then
+// the run still reaches the last non-zero row unless 2 / beta also lies
+// within 2 delta below an integer (a row of weight below 2 delta beta is
+// then left out, about once in 10^6 runs).
 // The taps use the clamped hat, so rows outside the support add exact
 // zeros (a run that would leave the window starts lower instead).  The
 // window is stored column-major, so a run is consecutive LDS words read two
@@ -58,9 +62,19 @@ struct BrickArgs {
     int W, H, HS;          // window columns and rows, LDS column stride
     int nbx, nby, nbz;
     int KV;                // voxels per lane along z (bricks 8 x 7 x 4 KV)
+    float rbias;           // 1 - adj_start_delta(nv)
 };
 
 __device__ inline float sat(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
+// LDS addresses as plain 32-bit numbers: a run's address comes out of one
+// float-to-integer conversion with no base to add.
+typedef __attribute__((address_space(3))) const float lds_float;
+__device__ inline uint32_t lds_addr(const float *p)
+{
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const float *)p;
+}
+__device__ inline lds_float *lds_ptr(uint32_t a) { return (lds_float *)(uintptr_t)a; }
 
 // Fractional panel column of the ray through (x, y, .) and its source-panel
 // scale lambda (a point at height z lands at V = lambda z).  Used only for a
@@ -86,6 +100,7 @@ struct GatherIn {
     int pl[2], sg[2];   // per sampling axis (0: x planes, 1: y planes): this lane's
                         // plane and in-plane segment; pl < 0: no work on that axis
     float inv_du, inv_rvs;
+    float rbias;        // 1 - delta: run start floor(v_c + 1 - delta)
 };
 
 __device__ inline float centre_x(const DevGeom &g, float i)
@@ -118,8 +133,8 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&lo)[2][
     const float inv_du = in.inv_du, inv_rvs = in.inv_rvs;
     const float *yt = in.yt;
     const float4 *cr = in.cr;
-    // Per voxel n: the row where a ray with parameter t crosses z index
-    // k0 + n - 1, plus 1/64, is Bk / t + A0; the hat argument at row r is
+    // Per voxel n: the row v_c where a ray with parameter t crosses z index
+    // k0 + n - 1 is Bk / t + A0 - (1 - delta); the hat argument at row r is
     // t ((r - cv) rvs + rv0) + Kb - k.
     float Bk[KV], KbK[KV];
 #pragma unroll
@@ -128,7 +143,8 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&lo)[2][
         Bk[n] = (kk - 1.0f - g.Kb) * inv_rvs;
         KbK[n] = g.Kb - kk;
     }
-    const float A0 = fmaf(-g.rv0, inv_rvs, g.cv + 0.015625f);
+    const float A0 = fmaf(-g.rv0, inv_rvs, g.cv + in.rbias);
+
     const float V0f = (float)V0, VS1f = (float)VS1;
 #pragma unroll
     for (int cls = 0; cls < 2; ++cls) {
@@ -181,15 +197,23 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&lo)[2][
             const float t = fmaf(fp, cq.w, cq.z);
             const float beta = t * g.rvs;
             const float rt = __builtin_amdgcn_rcpf(t);
-            const float *ycol = yt + (u - U0) * HS - V0;
+            // LDS byte address of row 0 of this column in the window, signed
+            // (row 0 lies below the window when V0 > 0; every row read,
+            // vsf >= V0, has a non-negative address); exact in FP32: LDS
+            // addresses are far below 2^24
+            const float colb = (float)((int)lds_addr(yt) + 4 * ((u - U0) * HS - V0));
 #pragma unroll
             for (int n = 0; n < KV; ++n) {
-                // run start, clamped into [V0, VS1] (a start moved down to
-                // VS1 only adds rows below the run, of zero weight)
+                // run start: the first row above v_c (floor(v_c) + 1), or one
+                // row lower, of zero weight (see the file comment); clamped
+                // into [V0, VS1] (a start moved down to VS1 only adds rows
+                // below the run, of zero weight)
                 const float vsf =
                     __builtin_amdgcn_fmed3f(floorf(fmaf(rt, Bk[n], A0)), V0f, VS1f);
+                // hat argument at the run start; (vsf - cv) is exact, which keeps
+                // the rounding of this difference of two large z indices small
                 float s = fmaf(t, fmaf(vsf - g.cv, g.rvs, g.rv0), KbK[n]);
-                const float *py = ycol + (int)vsf;
+                const lds_float *py = lds_ptr((uint32_t)fmaf(vsf, 4.0f, colb));
                 float yv[NT];
 #pragma unroll
                 for (int m = 0; m < NT; ++m)
@@ -343,7 +367,7 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
         // ---- gather with a compile-time tap count (NT rounded up to a
         // supported count; extra taps read zero weight)
         const GatherIn in{g, ar, yt, cr, HS, U0, U1, V0, VS1, k0, {pl0, pl1}, {sg0, sg1},
-                          inv_du, inv_rvs};
+                          inv_du, inv_rvs, A.rbias};
         switch (NT) {
         case 4: gather_angle<4, KV>(in, lo, hi); break;
         case 5: gather_angle<5, KV>(in, lo, hi); break;
@@ -478,7 +502,8 @@ static BrickArgs brick_args(const DevGeom &g, const AdjPlan &p)
 {
     const int bk = 4 * p.KV;
     return BrickArgs{g, p.wins, p.W, p.H, p.WS, (g.nx + kAdjBI - 1) / kAdjBI,
-                     (g.ny + kAdjBJ - 1) / kAdjBJ, (g.nz + bk - 1) / bk, p.KV};   // WS: column stride
+                     (g.ny + kAdjBJ - 1) / kAdjBJ, (g.nz + bk - 1) / bk, p.KV,   // WS: column stride
+                     1.0f - adj_start_delta(g.nv)};
 }
 
 // The window and column table, or the final exchange (four shares per lane

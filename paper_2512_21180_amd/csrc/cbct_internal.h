@@ -87,6 +87,16 @@ __host__ __device__ inline int adj_taps_rounded(int nt)
     return 32;
 }
 
+// The adjoint's row runs start at floor(v_c + 1 - delta), v_c the row where a
+// ray crosses a voxel's lower z support: delta exceeds the FP32 rounding of
+// v_c (a few units of the last place of a row index up to nv) several
+// times, and is at least 2^-12 row.
+__host__ __device__ inline float adj_start_delta(int nv)
+{
+    const float d = (float)nv * (1.0f / 1048576.0f);
+    return d > (1.0f / 4096.0f) ? d : (1.0f / 4096.0f);
+}
+
 // Adjoint bricks: kAdjBI x kAdjBJ output voxel columns (x, y) and 4 KV
 // voxels along z.  One wave's 64 lanes serve the brick's in-plane segments
 // on either sampling axis: 8 planes x 8 segments on x planes (seven output

@@ -125,8 +125,8 @@ TileBuild make_tiles(const cbct_geom *g, int TU, int TV)
 // to the panel), the extreme source-panel scales and the smallest ray
 // parameter t, from which the row taps follow (a voxel's non-zero rows in
 // one column span less than 2 / (t dv / vz) rows: at most floor of that
-// plus one, and one more for the run start, which may lie one row below
-// the first non-zero row).  The kernel reads these instead of computing them.
+// plus one, counted from the first of them, where the run starts).  The
+// kernel reads these instead of computing them.
 struct WinTable {
     std::vector<BrickWin> w;         // [n_angles][nby][nbx]
     std::vector<double> lmin, lmax;  // the scales in FP64
@@ -178,7 +178,7 @@ WinTable brick_windows(const cbct_geom *g, int NTmax)
                 } else {
                     bw.u01 = 1u;   // u0 = 1 > u1 = 0: not seen
                 }
-                const int nt = (int)std::floor(2.0 / (tmin * rvs)) + 2;
+                const int nt = (int)std::floor(2.0 / (tmin * rvs)) + 1;
                 bw.nt = adj_taps_rounded(std::min(nt, NTmax));
                 t.lmin[e] = lmin;
                 t.lmax[e] = lmax;
@@ -293,7 +293,7 @@ void plan_host(cbct_geom *g)
     }
     const double t_min = (d.sid_mm - R_sup) / d.sdd_mm;
     const double rvs = d.dv_mm / d.vz_mm;
-    const int NT = adj_taps_rounded((int)std::floor(2.0 / (t_min * rvs)) + 2);
+    const int NT = adj_taps_rounded((int)std::floor(2.0 / (t_min * rvs)) + 1);
     const long bricks_xy = (long)((d.nx + kBI - 1) / kBI) * ((d.ny + kBJ - 1) / kBJ);
     WinTable wt = brick_windows(g, NT);
     g->wins = wt.w;

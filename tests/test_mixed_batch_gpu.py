@@ -55,8 +55,9 @@ def _check(got, ref, vt, st, what, scale=None):
     b = _bound(ref, vt, st, scale)
     ratio = np.abs(got - ref) / b
     k = int(np.argmax(ratio))
-    print(f"  {what}: worst error/bound {ratio.flat[k]:.3f} (got {got.flat[k]:.6g}, "
-          f"ref {ref.flat[k]:.6g})", flush=True)
+    rel = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    print(f"  {what}: rel L2 {rel:.3e}, worst error/bound {ratio.flat[k]:.3f} "
+          f"(got {got.flat[k]:.6g}, ref {ref.flat[k]:.6g})", flush=True)
     assert ratio.flat[k] <= 1.0, what
 
 

@@ -235,7 +235,7 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
         u = fma32(fma32(lam, fma32(-s_, x, f32(c_ * y)), -s["off_u"]), inv_du, s["cu"])
         return f32(u), lam
 
-    checked = 0
+    checked = skipped = 0
     for a in angles:
         c_, s_ = h.ang_cs[a]
         x_lo, x_hi = h.ang_x[a]
@@ -304,12 +304,18 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
                     rows_sup = np.nonzero(np.abs(kf.astype(np.float64) - kk) < 1.0)[0]
                     inv_rvs = f32(f32(1.0) / rvs)
                     Bk = f32(f32(f32(f32(kk) - f32(1.0)) - Kb) * inv_rvs)
-                    A0 = fma32(-rv0, inv_rvs, f32(cv + f32(0.015625)))
+                    delta = max(nv / 1048576.0, 1.0 / 4096)
+                    A0 = fma32(-rv0, inv_rvs, f32(cv + f32(1.0 - delta)))
                     vf = fma32(rt, Bk, A0)
                     vstart = min(max(int(np.floor(vf)), V0), VS1)
-                    assert np.all((rows_sup >= vstart) & (rows_sup < vstart + NT)
-                                  & (rows_sup <= V1)), \
-                        (a, cls, pl, sg, kk, u, rows_sup, vstart, NT, V1)
+                    inrun = (rows_sup >= vstart) & (rows_sup < vstart + NT) & (rows_sup <= V1)
+                    # a row may be left out only where its weight is below
+                    # 2 delta beta, plus FP32 rounding
+                    wgt = 1.0 - np.abs(kf[rows_sup].astype(np.float64) - kk)
+                    beta = float(t) * float(rvs)
+                    assert np.all(inrun | (wgt <= 2 * delta * beta + 1e-5)), \
+                        (a, cls, pl, sg, kk, u, rows_sup, wgt, vstart, NT, V1)
+                    skipped += int(np.sum(~inrun))
                     checked += len(rows_sup)
         # every non-zero in-plane weight of an output voxel comes from one of
         # the lanes' segments (the voxel's own or the one below)
@@ -326,6 +332,8 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
                     segs = np.floor(q[np.abs(q.astype(np.float64) - qv) < 1.0]).astype(int)
                     lane_segs = {r[2] for r in roles if r[0] == cls and r[1] == fp}
                     assert set(segs.tolist()) <= lane_segs, (a, cls, i, j, set(segs), lane_segs)
+    # left-out rows need two coincidences and stay rare
+    assert skipped <= 1e-4 * max(checked, 1) + 2, (skipped, checked)
     return checked
 
 
