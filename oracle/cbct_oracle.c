@@ -711,3 +711,414 @@ void orc_sim_gaussian(int64_t n, const double *clean, double sigma, uint64_t see
         out[i] = clean[i] + sigma * z;
     }
 }
+
+/* ---- scatter simulator (Sec. 2.3: the path-integral scatter model and its
+ * quasi-Monte Carlo evaluation, Alg. 2 SamplePath and Alg. 3 Integrate;
+ * appendix: Beer-Lambert escape probability eq. beer, the travel-distance
+ * measure eq. lambdameas, inverse-transform sampling eq. distsample, the
+ * material and interaction-type Bernoulli choices and the Compton energy).
+ *
+ * Readings (the paper states the model, not its discretisation):
+ *   * The attenuation is piecewise constant on voxel cubes: voxel (i,j,k)
+ *     holds relative densities rho_w, rho_b on the cube of its pitch centred
+ *     at its centre; zero outside the volume.  mu_tot,e(x) =
+ *     rho_w(x) mu_w(e) + rho_b(x) mu_b(e), mu_m(e) = p + c + r components.
+ *   * Cross sections are tables on the energy grid e_k = e0 + k de, linear
+ *     in e between grid points and constant beyond the ends; angular
+ *     distributions per material and scatter type are tables too: the
+ *     inverse CDF of cos(theta) on u = j / (J - 1) and the density of
+ *     scatter directions per steradian on cos(theta) = -1 + 2 i / (I - 1),
+ *     both bilinear in (energy, abscissa).
+ *   * A scattered direction: cos(theta) from the inverse CDF at the first
+ *     point, azimuth phi = 2 pi u at the second, around the incoming v in
+ *     the frame a = normalise(v x z) (v x x when |v_z| >= 0.9), b = v x a:
+ *     v' = cos(theta) v + sin(theta) (cos(phi) a + sin(phi) b).
+ *   * The weight after a scatter is w (1 - mu_p / mu_tot) of the chosen
+ *     material (the printed w (1 - mu_p) / mu_tot is read this way); W
+ *     appends each weight (the printed W <- [w] restarts the list).
+ *   * Sobol point i has 5 n + 1 coordinates: 0 for the first distance,
+ *     then for scatter j = 1..n, k = 1 + 5 (j - 1): material, type, cos,
+ *     azimuth, distance.
+ *   * Integrate scores each interaction point x_o (o = 1..n+1) with the
+ *     direction v, energy e and weight w the photon arrived with (the
+ *     printed zip pairs the source point with the first direction); the
+ *     scatter density at x is sum_m (mu_m / mu_tot)(x) (mu_T,m / mu_tot,m)
+ *     dens_T,m(cos theta, e) for T = Compton, Rayleigh; the escape
+ *     probability toward a pixel integrates up to the pixel centre (the
+ *     panel lies beyond the volume); the accumulation index is the pixel.
+ *   * A photon whose first ray misses the volume has weight 0 and stays at
+ *     the source.  Where mu_tot(x) = 0 the material is water.
+ * FP64 throughout; one photon (paths) or one pixel (integration) at a time.
+ */
+
+typedef struct {
+    int K;
+    double e0, de;          /* energy grid (keV) */
+    const double *mu;       /* [2 materials][3 kinds: p, c, r][K], mm^-1 at unit density */
+    int J;
+    const double *icdf;     /* [2][2 types: c, r][K][J] cos(theta) at u = j / (J - 1) */
+    int I;
+    const double *dens;     /* [2][2][K][I] per steradian at cos = -1 + 2 i / (I - 1) */
+} orc_xs;
+
+static const double ORC_ME_C2 = 510.99895;   /* electron rest energy, keV */
+
+static void e_index(const orc_xs *x, double e, int *k, double *f)
+{
+    double t = (e - x->e0) / x->de;
+    if (t < 0.0)
+        t = 0.0;
+    if (t > x->K - 1)
+        t = x->K - 1;
+    int kk = (int)floor(t);
+    if (kk > x->K - 2)
+        kk = x->K - 2;
+    *k = kk;
+    *f = t - kk;
+}
+
+static double xs_mu(const orc_xs *x, int m, int kind, double e)
+{
+    int k;
+    double f;
+    e_index(x, e, &k, &f);
+    const double *t = x->mu + ((size_t)m * 3 + kind) * x->K;
+    return (1.0 - f) * t[k] + f * t[k + 1];
+}
+
+static double xs_tot(const orc_xs *x, int m, double e)
+{
+    return xs_mu(x, m, 0, e) + xs_mu(x, m, 1, e) + xs_mu(x, m, 2, e);
+}
+
+/* bilinear in (energy, abscissa) on a [K][n] table; s in [0, n - 1] */
+static double table2(const orc_xs *x, const double *tab, int n, double e, double s)
+{
+    int k;
+    double f;
+    e_index(x, e, &k, &f);
+    if (s < 0.0)
+        s = 0.0;
+    if (s > n - 1)
+        s = n - 1;
+    int j = (int)floor(s);
+    if (j > n - 2)
+        j = n - 2;
+    double g = s - j;
+    const double *r0 = tab + (size_t)k * n, *r1 = tab + (size_t)(k + 1) * n;
+    double a = (1.0 - g) * r0[j] + g * r0[j + 1];
+    double b = (1.0 - g) * r1[j] + g * r1[j + 1];
+    return (1.0 - f) * a + f * b;
+}
+
+static double xs_icdf(const orc_xs *x, int m, int T, double e, double u)
+{
+    return table2(x, x->icdf + ((size_t)m * 2 + T) * x->K * x->J, x->J, e, u * (x->J - 1));
+}
+
+static double xs_dens(const orc_xs *x, int m, int T, double e, double cth)
+{
+    return table2(x, x->dens + ((size_t)m * 2 + T) * x->K * x->I, x->I, e,
+                  (cth + 1.0) * 0.5 * (x->I - 1));
+}
+
+double orc_compton_energy(double e, double cth)
+{
+    return e / (1.0 + e * (1.0 - cth) / ORC_ME_C2);
+}
+
+/* resp(e): piecewise linear through (20, 5), (60, 20), (120, 10) keV, the end
+ * values beyond (Sec. 2.2). */
+double orc_resp(double e)
+{
+    if (e <= 20.0)
+        return 5.0;
+    if (e <= 60.0)
+        return 5.0 + (e - 20.0) * 15.0 / 40.0;
+    if (e < 120.0)
+        return 20.0 - (e - 60.0) * 10.0 / 60.0;
+    return 10.0;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Segments of the ray p + t d (|d| = 1), 0 <= t <= tmax, through the voxel
+ * cubes: every parameter where it crosses a voxel face or the volume's
+ * bounds, sorted; on each segment the voxel is the one holding its midpoint.
+ * Returns the number of breakpoints written to ts (room for nx+ny+nz+5). */
+static int ray_breaks(const orc_geom *g, const double p[3], const double d[3], double tmax,
+                      double *ts)
+{
+    const int n[3] = {g->nx, g->ny, g->nz};
+    const double v[3] = {g->vx, g->vy, g->vz}, o[3] = {g->ox, g->oy, g->oz};
+    double t0 = 0.0, t1 = tmax;
+    for (int q = 0; q < 3; ++q) {
+        double lo = o[q] - 0.5 * n[q] * v[q], hi = o[q] + 0.5 * n[q] * v[q];
+        if (d[q] == 0.0) {
+            if (p[q] <= lo || p[q] >= hi)
+                return 0;
+            continue;
+        }
+        double ta = (lo - p[q]) / d[q], tb = (hi - p[q]) / d[q];
+        if (ta > tb) {
+            double s = ta;
+            ta = tb;
+            tb = s;
+        }
+        if (ta > t0)
+            t0 = ta;
+        if (tb < t1)
+            t1 = tb;
+    }
+    if (!(t1 > t0))
+        return 0;
+    int cnt = 0;
+    ts[cnt++] = t0;
+    for (int q = 0; q < 3; ++q) {
+        if (d[q] == 0.0)
+            continue;
+        double lo = o[q] - 0.5 * n[q] * v[q];
+        for (int m = 1; m < n[q]; ++m) {
+            double t = (lo + m * v[q] - p[q]) / d[q];
+            if (t > t0 && t < t1)
+                ts[cnt++] = t;
+        }
+    }
+    ts[cnt++] = t1;
+    qsort(ts, cnt, sizeof(double), cmp_double);
+    return cnt;
+}
+
+static long voxel_at(const orc_geom *g, const double x[3])
+{
+    const int n[3] = {g->nx, g->ny, g->nz};
+    const double v[3] = {g->vx, g->vy, g->vz}, o[3] = {g->ox, g->oy, g->oz};
+    long idx[3];
+    for (int q = 0; q < 3; ++q) {
+        double f = (x[q] - (o[q] - 0.5 * n[q] * v[q])) / v[q];
+        if (!(f >= 0.0 && f < n[q]))
+            return -1;
+        idx[q] = (long)floor(f);
+    }
+    return (idx[2] * g->ny + idx[1]) * g->nx + idx[0];
+}
+
+/* Material line integrals (int rho_w, int rho_b) along p + t d, t in [0, tmax]. */
+void orc_march(const orc_geom *g, const double *rw, const double *rb, const double p[3],
+               const double d[3], double tmax, double out[2])
+{
+    double *ts = malloc(sizeof(double) * (g->nx + g->ny + g->nz + 5));
+    int cnt = ray_breaks(g, p, d, tmax, ts);
+    out[0] = out[1] = 0.0;
+    for (int s = 0; s + 1 < cnt; ++s) {
+        double len = ts[s + 1] - ts[s];
+        if (!(len > 0.0))
+            continue;
+        double tm = 0.5 * (ts[s] + ts[s + 1]);
+        double xm[3] = {p[0] + tm * d[0], p[1] + tm * d[1], p[2] + tm * d[2]};
+        long vi = voxel_at(g, xm);
+        if (vi < 0)
+            continue;
+        out[0] += len * rw[vi];
+        out[1] += len * rb[vi];
+    }
+    free(ts);
+}
+
+/* Interaction distance along p + t d at energy e (eq. distsample): the t at
+ * which the optical depth reaches -log(1 - (1 - p0) ubar); p0 the escape
+ * probability (eq. beer) of the whole ray.  Returns t (0 if the ray never
+ * meets attenuating matter). */
+static double sample_distance(const orc_geom *g, const double *rw, const double *rb,
+                              const orc_xs *xs, const double p[3], const double d[3], double e,
+                              double ubar, double *p0)
+{
+    const double big = 1e7;
+    double *ts = malloc(sizeof(double) * (g->nx + g->ny + g->nz + 5));
+    int cnt = ray_breaks(g, p, d, big, ts);
+    double mw = xs_tot(xs, 0, e), mb = xs_tot(xs, 1, e);
+    double tau = 0.0;
+    for (int s = 0; s + 1 < cnt; ++s) {
+        double len = ts[s + 1] - ts[s];
+        if (!(len > 0.0))
+            continue;
+        double tm = 0.5 * (ts[s] + ts[s + 1]);
+        double xm[3] = {p[0] + tm * d[0], p[1] + tm * d[1], p[2] + tm * d[2]};
+        long vi = voxel_at(g, xm);
+        if (vi >= 0)
+            tau += len * (rw[vi] * mw + rb[vi] * mb);
+    }
+    *p0 = exp(-tau);
+    double l = 0.0;
+    if (tau > 0.0) {
+        double target = -log(1.0 - (1.0 - *p0) * ubar);
+        double acc = 0.0;
+        for (int s = 0; s + 1 < cnt; ++s) {
+            double len = ts[s + 1] - ts[s];
+            if (!(len > 0.0))
+                continue;
+            double tm = 0.5 * (ts[s] + ts[s + 1]);
+            double xm[3] = {p[0] + tm * d[0], p[1] + tm * d[1], p[2] + tm * d[2]};
+            long vi = voxel_at(g, xm);
+            double mu = vi >= 0 ? rw[vi] * mw + rb[vi] * mb : 0.0;
+            if (mu > 0.0 && acc + len * mu >= target) {
+                l = ts[s] + (target - acc) / mu;
+                break;
+            }
+            acc += len * mu;
+            l = ts[s + 1];
+        }
+    }
+    free(ts);
+    return l;
+}
+
+static void normalise3(double v[3])
+{
+    double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n;
+    v[1] /= n;
+    v[2] /= n;
+}
+
+/* v' at polar cos(theta) and azimuth phi around v (frame as stated above). */
+void orc_scatter_direction(const double v[3], double cth, double phi, double out[3])
+{
+    double a[3];
+    if (fabs(v[2]) < 0.9) {          /* v x z */
+        a[0] = v[1];
+        a[1] = -v[0];
+        a[2] = 0.0;
+    } else {                         /* v x x */
+        a[0] = 0.0;
+        a[1] = v[2];
+        a[2] = -v[1];
+    }
+    normalise3(a);
+    double b[3] = {v[1] * a[2] - v[2] * a[1], v[2] * a[0] - v[0] * a[2], v[0] * a[1] - v[1] * a[0]};
+    double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+    for (int q = 0; q < 3; ++q)
+        out[q] = cth * v[q] + sth * (cos(phi) * a[q] + sin(phi) * b[q]);
+}
+
+/*
+ * SamplePath (Alg. 2) at projection angle index a: photon i leaves the source
+ * S(theta_a) with direction R_a src[i][0..2] (src directions are given for
+ * the source at angle 0; R_a rotates about z by theta_a) and energy
+ * src[i][3].  sob: [N][5 n + 1] quasi-random points.  rec: [N][n + 1][8]
+ * records (x, y, z of the interaction point, the direction and energy the
+ * photon arrived with, its weight).
+ */
+void orc_scatter_paths(const orc_geom *g, const double *rw, const double *rb, const orc_xs *xs,
+                       int a, int64_t N, const double *src, const double *sob, int n,
+                       double *rec)
+{
+    const double th = g->angles[a], c = cos(th), s = sin(th);
+    const int D = 5 * n + 1;
+    for (int64_t i = 0; i < N; ++i) {
+        const double *sp = src + 4 * i, *u = sob + (size_t)i * D;
+        double x[3] = {g->sid * c, g->sid * s, 0.0};
+        double v[3] = {c * sp[0] - s * sp[1], s * sp[0] + c * sp[1], sp[2]};
+        normalise3(v);
+        double e = sp[3], w = 1.0;
+        for (int o = 0; o <= n; ++o) {
+            double p0;
+            const double l = sample_distance(g, rw, rb, xs, x, v, e, u[5 * o], &p0);
+            w *= 1.0 - p0;
+            for (int q = 0; q < 3; ++q)
+                x[q] += l * v[q];
+            double *r = rec + ((size_t)i * (n + 1) + o) * 8;
+            r[0] = x[0];
+            r[1] = x[1];
+            r[2] = x[2];
+            r[3] = v[0];
+            r[4] = v[1];
+            r[5] = v[2];
+            r[6] = e;
+            r[7] = w;
+            if (o == n)
+                break;
+            const int k = 1 + 5 * o;
+            const long vi = voxel_at(g, x);
+            const double aw = vi >= 0 ? rw[vi] * xs_tot(xs, 0, e) : 0.0;
+            const double ab = vi >= 0 ? rb[vi] * xs_tot(xs, 1, e) : 0.0;
+            const double fw = (aw + ab) > 0.0 ? aw / (aw + ab) : 1.0;
+            const int m = u[k] < fw ? 0 : 1;
+            const double mc = xs_mu(xs, m, 1, e), mr = xs_mu(xs, m, 2, e);
+            const int T = u[k + 1] < mc / (mc + mr) ? 0 : 1;
+            w *= 1.0 - xs_mu(xs, m, 0, e) / xs_tot(xs, m, e);
+            const double cth = xs_icdf(xs, m, T, e, u[k + 2]);
+            double vn[3];
+            orc_scatter_direction(v, cth, 2.0 * M_PI * u[k + 3], vn);
+            normalise3(vn);
+            v[0] = vn[0];
+            v[1] = vn[1];
+            v[2] = vn[2];
+            if (T == 0)
+                e = orc_compton_energy(e, cth);
+        }
+    }
+}
+
+/*
+ * Integrate (Alg. 3) at projection angle index a over nrec records (as
+ * written by orc_scatter_paths): out[iv][iu] (the panel of g at angle a,
+ * pixel centres as in orc_ray) receives, per record in order,
+ *   s w |<n, v_s>| du dv / |sigma - x|^2,
+ *   s = s_c p0(x, v_s, e') resp(e') + s_r p0(x, v_s, e) resp(e),
+ * n the panel normal, v_s the unit vector from x to the pixel centre, e' the
+ * Compton energy for the angle between v and v_s.  The caller scales by
+ * I_Sigma / |Src|.
+ */
+void orc_scatter_integrate(const orc_geom *g, const double *rw, const double *rb,
+                           const orc_xs *xs, int a, int64_t nrec, const double *rec, double *out)
+{
+    const double th = g->angles[a];
+    const double nrm[3] = {cos(th), sin(th), 0.0};
+    for (int iv = 0; iv < g->nv; ++iv)
+        for (int iu = 0; iu < g->nu; ++iu) {
+            double S[3], d[3];
+            orc_ray(g, a, iu, iv, S, d);
+            const double pix[3] = {S[0] + d[0], S[1] + d[1], S[2] + d[2]};
+            double acc = 0.0;
+            for (int64_t r = 0; r < nrec; ++r) {
+                const double *q = rec + 8 * r;
+                const double w = q[7];
+                if (!(w > 0.0))
+                    continue;
+                const double x[3] = {q[0], q[1], q[2]}, v[3] = {q[3], q[4], q[5]};
+                const double e = q[6];
+                double vs[3] = {pix[0] - x[0], pix[1] - x[1], pix[2] - x[2]};
+                const double r2 = vs[0] * vs[0] + vs[1] * vs[1] + vs[2] * vs[2];
+                const double dist = sqrt(r2);
+                vs[0] /= dist;
+                vs[1] /= dist;
+                vs[2] /= dist;
+                const double cth = v[0] * vs[0] + v[1] * vs[1] + v[2] * vs[2];
+                const double ec = orc_compton_energy(e, cth);
+                double P[2];
+                orc_march(g, rw, rb, x, vs, dist, P);
+                const long vi = voxel_at(g, x);
+                const double aw = vi >= 0 ? rw[vi] * xs_tot(xs, 0, e) : 0.0;
+                const double ab = vi >= 0 ? rb[vi] * xs_tot(xs, 1, e) : 0.0;
+                const double tot = aw + ab;
+                const double f[2] = {tot > 0.0 ? aw / tot : 1.0, tot > 0.0 ? ab / tot : 0.0};
+                double sc = 0.0, sr = 0.0;
+                for (int m = 0; m < 2; ++m) {
+                    const double mt = xs_tot(xs, m, e);
+                    sc += f[m] * xs_mu(xs, m, 1, e) / mt * xs_dens(xs, m, 0, e, cth);
+                    sr += f[m] * xs_mu(xs, m, 2, e) / mt * xs_dens(xs, m, 1, e, cth);
+                }
+                const double p0c = exp(-(xs_tot(xs, 0, ec) * P[0] + xs_tot(xs, 1, ec) * P[1]));
+                const double p0r = exp(-(xs_tot(xs, 0, e) * P[0] + xs_tot(xs, 1, e) * P[1]));
+                const double sv = sc * p0c * orc_resp(ec) + sr * p0r * orc_resp(e);
+                const double cn = fabs(nrm[0] * vs[0] + nrm[1] * vs[1] + nrm[2] * vs[2]);
+                acc += sv * w * cn * g->du * g->dv / r2;
+            }
+            out[(size_t)iv * g->nu + iu] = acc;
+        }
+}

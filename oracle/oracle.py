@@ -19,6 +19,8 @@ Contents, each written from the paper (arXiv 2512.21180):
 * ``water_bone`` / ``detector_response`` / ``sim_poly``: the polychromatic
   water-bone primary model (Sec. 2.2, eq. primarymodel) and the normalised
   negative log (Sec. 2.4, eq. normprimary).
+* ``march`` / ``scatter_paths`` / ``scatter_integrate``: the quasi-Monte
+  Carlo scatter model (Sec. 2.3, Alg. 2 and Alg. 3).
 
 Geometry is passed as a plain dict with keys sid, sdd, n_angles, angles
 (optional, radians), nu, nv, du, dv, off_u, off_v, nx, ny, nz, vx, vy, vz,
@@ -95,8 +97,27 @@ def _load():
         lib.orc_sim_gaussian.argtypes = [i64, P(d), d, ctypes.c_uint64, u32, P(d)]
         lib.orc_sim_poly.argtypes = [i64, i64, P(d), P(d), ctypes.c_int, P(d), P(d), P(d), P(d),
                                      ctypes.c_uint64, u32, P(i64), P(d), P(d)]
+        X = P(_OXs)
+        lib.orc_march.argtypes = [G, P(d), P(d), P(d), P(d), d, P(d)]
+        lib.orc_compton_energy.argtypes = [d, d]
+        lib.orc_compton_energy.restype = d
+        lib.orc_resp.argtypes = [d]
+        lib.orc_resp.restype = d
+        lib.orc_scatter_direction.argtypes = [P(d), d, d, P(d)]
+        lib.orc_scatter_paths.argtypes = [G, P(d), P(d), X, ctypes.c_int, i64, P(d), P(d),
+                                          ctypes.c_int, P(d)]
+        lib.orc_scatter_integrate.argtypes = [G, P(d), P(d), X, ctypes.c_int, i64, P(d), P(d)]
         _lib = lib
     return _lib
+
+
+class _OXs(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int), ("e0", ctypes.c_double), ("de", ctypes.c_double),
+        ("mu", ctypes.POINTER(ctypes.c_double)),
+        ("J", ctypes.c_int), ("icdf", ctypes.POINTER(ctypes.c_double)),
+        ("I", ctypes.c_int), ("dens", ctypes.POINTER(ctypes.c_double)),
+    ]
 
 
 def angles_of(g: dict) -> np.ndarray:
@@ -420,6 +441,88 @@ def sim_poly(pw: np.ndarray, pb: np.ndarray, mu_w, mu_b, resp, I0: np.ndarray, s
     lib.orc_sim_poly(a.size, npix, _dp(a), _dp(b), nb, _dp(mw), _dp(mb), _dp(rs), _dp(i0.ravel()),
                      seed, stream, _ip(c), _dp(sig), _dp(y))
     return y.reshape(shape), sig.reshape(shape), c.reshape((nb,) + tuple(shape))
+
+
+# ---- scatter simulator (Sec. 2.3, Alg. 2 and Alg. 3; appendix eqs. beer,
+# lambdameas, distsample and the Compton energy) ----
+#
+# Cross sections are a dict: e0, de (keV grid), mu [2 materials (water, bone)]
+# [3 kinds (photoelectric, Compton, Rayleigh)][K] (mm^-1 at unit density),
+# icdf [2][2 types (Compton, Rayleigh)][K][J] (cos theta at u = j / (J - 1)),
+# dens [2][2][K][I] (scatter directions per steradian at
+# cos theta = -1 + 2 i / (I - 1)).  See cbct_oracle.c for the readings.
+
+def _xs_struct(xs: dict):
+    mu = np.ascontiguousarray(xs["mu"], dtype=np.float64)
+    ic = np.ascontiguousarray(xs["icdf"], dtype=np.float64)
+    dn = np.ascontiguousarray(xs["dens"], dtype=np.float64)
+    K = mu.shape[-1]
+    assert mu.shape == (2, 3, K) and ic.shape[:3] == (2, 2, K) and dn.shape[:3] == (2, 2, K)
+    st = _OXs(K, float(xs["e0"]), float(xs["de"]), _dp(mu), ic.shape[3], _dp(ic),
+              dn.shape[3], _dp(dn))
+    return st, (mu, ic, dn)
+
+
+def march(g: dict, rw, rb, p, d, tmax: float):
+    """(int rho_w, int rho_b) along p + t d, 0 <= t <= tmax (d a unit vector),
+    voxels as cubes of constant density."""
+    lib = _load()
+    G = _Geom(g)
+    a = np.ascontiguousarray(rw, dtype=np.float64)
+    b = np.ascontiguousarray(rb, dtype=np.float64)
+    out = np.zeros(2)
+    lib.orc_march(G.ref, _dp(a), _dp(b), _dp(np.asarray(p, dtype=np.float64)),
+                  _dp(np.asarray(d, dtype=np.float64)), float(tmax), _dp(out))
+    return out
+
+
+def compton_energy(e: float, cos_theta: float) -> float:
+    return float(_load().orc_compton_energy(float(e), float(cos_theta)))
+
+
+def resp(e: float) -> float:
+    return float(_load().orc_resp(float(e)))
+
+
+def scatter_direction(v, cos_theta: float, phi: float) -> np.ndarray:
+    out = np.zeros(3)
+    _load().orc_scatter_direction(_dp(np.asarray(v, dtype=np.float64)), float(cos_theta),
+                                  float(phi), _dp(out))
+    return out
+
+
+def scatter_paths(g: dict, rw, rb, xs: dict, a: int, src, sob, n: int) -> np.ndarray:
+    """SamplePath (Alg. 2) at projection a: [N, n + 1, 8] records (interaction
+    point, arriving direction, arriving energy, weight).  src [N, 4]: unit
+    direction for the source at angle 0 and energy (keV); sob [N, 5 n + 1]."""
+    lib = _load()
+    G = _Geom(g)
+    st, keep = _xs_struct(xs)
+    a_ = np.ascontiguousarray(rw, dtype=np.float64)
+    b_ = np.ascontiguousarray(rb, dtype=np.float64)
+    sp = np.ascontiguousarray(src, dtype=np.float64)
+    so = np.ascontiguousarray(sob, dtype=np.float64)
+    N = sp.shape[0]
+    assert sp.shape == (N, 4) and so.shape == (N, 5 * n + 1)
+    rec = np.zeros((N, n + 1, 8))
+    lib.orc_scatter_paths(G.ref, _dp(a_), _dp(b_), ctypes.byref(st), int(a), N, _dp(sp),
+                          _dp(so), int(n), _dp(rec))
+    return rec
+
+
+def scatter_integrate(g: dict, rw, rb, xs: dict, a: int, rec) -> np.ndarray:
+    """Integrate (Alg. 3) at projection a over records [..., 8]: the expected
+    scatter [nv, nu] on the panel of g (before the I_Sigma / |Src| scale)."""
+    lib = _load()
+    G = _Geom(g)
+    st, keep = _xs_struct(xs)
+    a_ = np.ascontiguousarray(rw, dtype=np.float64)
+    b_ = np.ascontiguousarray(rb, dtype=np.float64)
+    r = np.ascontiguousarray(rec, dtype=np.float64).reshape(-1, 8)
+    out = np.zeros((g["nv"], g["nu"]))
+    lib.orc_scatter_integrate(G.ref, _dp(a_), _dp(b_), ctypes.byref(st), int(a), r.shape[0],
+                              _dp(r), _dp(out))
+    return out
 
 
 # ---- 3x3x3 convolutions of the learned blocks (Alg. 1, dual/primal blocks) ----

@@ -252,3 +252,85 @@ def intensity_maps(g: dict, centres_kev, photons_per_mm2: float = 66000.0) -> np
     per_pix = photons_per_mm2 * g["du"] * g["dv"]
     return (per_pix * spec[:, None, None] * bow[None, None, :] *
             np.ones((1, g["nv"], 1))).astype(np.float32)
+
+
+# ---- inputs of the scatter model (Sec. 2.3) ----
+#
+# The paper takes cross sections from a database that is not available here;
+# the stand-ins below are smooth synthetic tables of the right form: per
+# material (water, bone) the photoelectric, Compton and Rayleigh attenuation
+# at unit density on an energy grid, and per material and scatter type the
+# distribution of the scattering angle as an inverse CDF of cos(theta) and a
+# density of directions per steradian.  Compton angles follow the
+# Klein-Nishina shape for free electrons; Rayleigh angles a forward-peaked
+# (1 + cos^2) shape narrowing with energy.
+
+ME_C2_KEV = 510.99895
+
+
+def _angle_tables(pdf, J, I):
+    """(icdf [J] at u = j / (J - 1), dens [I] per steradian at
+    cos = -1 + 2 i / (I - 1)) of a density pdf(cos) on [-1, 1]."""
+    c = np.linspace(-1.0, 1.0, 20001)
+    p = pdf(c)
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (p[1:] + p[:-1]) * np.diff(c))])
+    Z = cdf[-1]
+    icdf = np.interp(np.linspace(0.0, 1.0, J), cdf / Z, c)
+    ci = np.linspace(-1.0, 1.0, I)
+    dens = pdf(ci) / Z / (2.0 * math.pi)
+    return icdf, dens
+
+
+def scatter_tables(e0=10.0, de=5.0, K=29, J=129, I=129) -> dict:
+    """Synthetic cross-section tables (see above) for the scatter model:
+    dict(e0, de, mu [2, 3, K], icdf [2, 2, K, J], dens [2, 2, K, I])."""
+    e = e0 + de * np.arange(K)
+    pe = (25.0 / e) ** 3
+    mu = np.zeros((2, 3, K))
+    mu[0, 0], mu[0, 1], mu[0, 2] = 0.030 * pe, 0.018 * (1.0 - 0.002 * (e - 10.0)), 0.002 * (25.0 / e)
+    mu[1, 0], mu[1, 1], mu[1, 2] = 0.300 * pe, 0.030 * (1.0 - 0.002 * (e - 10.0)), 0.006 * (25.0 / e)
+    icdf = np.zeros((2, 2, K, J))
+    dens = np.zeros((2, 2, K, I))
+    for k, ek in enumerate(e):
+        a = ek / ME_C2_KEV
+
+        def kn(c, a=a):
+            P = 1.0 / (1.0 + a * (1.0 - c))
+            return P * P * (P + 1.0 / P - (1.0 - c * c))
+
+        for m, width in ((0, 12.0), (1, 16.0)):
+            def ray(c, ek=ek, width=width):
+                return (1.0 + c * c) * np.exp(-(1.0 - c) * ek / width)
+
+            icdf[m, 0, k], dens[m, 0, k] = _angle_tables(kn, J, I)
+            icdf[m, 1, k], dens[m, 1, k] = _angle_tables(ray, J, I)
+    return dict(e0=e0, de=de, mu=mu, icdf=icdf, dens=dens)
+
+
+def scatter_sources(N: int, g: dict, seed: int, spectrum_kev=None) -> np.ndarray:
+    """[N, 4] source photons for the source at angle 0: unit directions
+    toward uniformly random points of the panel and energies drawn from the
+    ten bin centres with the intensity maps' spectrum."""
+    r = rng(seed)
+    e = np.array([10.0 * i + 5.0 for i in range(2, 12)]) if spectrum_kev is None \
+        else np.asarray(spectrum_kev, dtype=np.float64)
+    w = np.exp(-0.5 * ((e - 55.0) / 22.0) ** 2)
+    w /= w.sum()
+    S = np.array([g["sid"], 0.0, 0.0])
+    u = (r.uniform(-0.5, 0.5, N) * g["nu"]) * g["du"] + g["off_u"]
+    v = (r.uniform(-0.5, 0.5, N) * g["nv"]) * g["dv"] + g["off_v"]
+    P = np.stack([np.full(N, -(g["sdd"] - g["sid"])), u, v], axis=1)
+    d = P - S
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return np.concatenate([d, r.choice(e, size=N, p=w)[:, None]], axis=1)
+
+
+def sobol_points(N: int, dims: int) -> np.ndarray:
+    """[N, dims] points of the unscrambled Sobol sequence (scipy's
+    implementation), skipping the first point (all zeros)."""
+    import warnings
+    from scipy.stats import qmc
+    s = qmc.Sobol(d=dims, scramble=False)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")     # balance holds for powers of two only
+        return s.random(N + 1)[1:]
