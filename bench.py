@@ -450,11 +450,80 @@ def measure_convs(reps=5):
     return res
 
 
+def measure_simulators(reps=3):
+    """HIP-event times of the two projection-data simulators beyond the
+    monochromatic one, at the clinical geometry with synthetic tables:
+
+    * polychromatic primary (NEXT-3): water/bone densities of a 256^3 HU
+      phantom, their two line integrals in one two-channel forward projection
+      (360 angles, 512^2 panel), and the ten-bin Poisson signal with its
+      normalised log; the Poisson kernel reads two FP32 line integrals and
+      writes y per element (12 B; the bin maps stay in the caches);
+    * scatter (NEXT-4) for one projection: path sampling of 4096 source
+      photons with two scatters each, and integration of the 3 x 4096 records
+      toward a 128^2 panel at 3.2 mm (a quarter of the primary resolution),
+      one march per record and pixel."""
+    import numpy as np
+    import torch
+    from paper_2512_21180_amd import cbct, simulate
+    from paper_2512_21180_amd import workloads as W
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    g = W.C2
+    geo = cbct.Geometry(g)
+    hu = torch.tensor(W.hu_phantom(g, 2025), device="cuda")
+    c, resp = cbct.poly_bins()
+    mw, mb = W.poly_tables(c)
+    I0 = torch.tensor(W.intensity_maps(g, c), device="cuda")
+    rho = cbct.water_bone(hu)
+    p = cbct.forward(geo, rho)
+    t_wb = timed(lambda: cbct.water_bone(hu, out=rho))
+    t_fw = timed(lambda: cbct.forward(geo, rho, out=p))
+    t_po = timed(lambda: cbct.sim_poly(p[0], p[1], mw, mb, resp, I0, 7, 0))
+    n_el = p[0].numel()
+    poly = {"water_bone_ms": round(t_wb * 1e3, 3), "forward_2ch_ms": round(t_fw * 1e3, 3),
+            "poisson_10_bins_ms": round(t_po * 1e3, 3),
+            "poisson_elements_per_s": round(n_el / t_po, 1),
+            "poisson_hbm_TBps": round(12 * n_el / t_po / 1e12, 3),
+            "total_ms": round((t_wb + t_fw + t_po) * 1e3, 3)}
+    print(json.dumps({"poly": poly}), file=sys.stderr, flush=True)
+    del p, I0
+    torch.cuda.empty_cache()
+
+    gs = W.geometry(360, 128, 128, 3.2, 3.2, 256, 256, 256, 2.0, off_u=115.0)
+    geos = cbct.Geometry(gs)
+    xs = cbct.ScatterTables(W.scatter_tables(), "cuda")
+    N, n = 4096, 2
+    src = torch.tensor(W.scatter_sources(N, gs, 11).astype(np.float32), device="cuda")
+    qmc = torch.tensor(W.sobol_points(N, 5 * n + 1).astype(np.float32), device="cuda")
+    rec = cbct.scatter_paths(geos, rho, xs, 0, src, qmc, n)
+    img = cbct.scatter_integrate(geos, rho, xs, 0, rec)
+    t_pa = timed(lambda: cbct.scatter_paths(geos, rho, xs, 0, src, qmc, n, out=rec))
+    t_in = timed(lambda: cbct.scatter_integrate(geos, rho, xs, 0, rec, out=img))
+    scat = {"photons": N, "scatters": n, "panel": [128, 128],
+            "paths_ms": round(t_pa * 1e3, 3), "integrate_ms": round(t_in * 1e3, 3),
+            "record_pixel_pairs_per_s": round(N * (n + 1) * 128 * 128 / t_in, 1)}
+    print(json.dumps({"scatter": scat}), file=sys.stderr, flush=True)
+    return {"poly_primary_c2": poly, "scatter_one_projection": scat}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sims", action="store_true",
+                    help="time the polychromatic primary and the scatter simulators instead")
     ap.add_argument("--convs", action="store_true",
                     help="time the learned blocks' convolution kernels at the net's grids instead")
     ap.add_argument("--peaks", action="store_true",
@@ -490,6 +559,9 @@ def main():
     torch.cuda.set_device(0)
     if args.peaks:
         print(json.dumps(measure_peaks()), flush=True)
+        return
+    if args.sims:
+        print(json.dumps(measure_simulators()), flush=True)
         return
     if args.convs:
         print(json.dumps(measure_convs()), flush=True)

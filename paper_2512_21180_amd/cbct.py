@@ -75,6 +75,9 @@ def _load():
     lib.cbct_water_bone.argtypes = [sz, vp, vp, vp, vp]
     lib.cbct_poly_bins.argtypes = [i32, vp, vp, ctypes.POINTER(i32)]
     lib.cbct_sim_poly.argtypes = [sz, sz, vp, vp, i32, vp, vp, vp, vp, u64, u32, vp, vp, vp, vp]
+    i64 = ctypes.c_int64
+    lib.cbct_scatter_paths.argtypes = [vp, vp, vp, i32, i64, vp, vp, i32, vp, vp]
+    lib.cbct_scatter_integrate.argtypes = [vp, vp, vp, i32, i64, vp, vp, vp]
     fl = ctypes.c_float
     lib.cbct_pack16.argtypes = [sz, i32, ctypes.POINTER(vp), ctypes.POINTER(fl), vp, vp]
     lib.cbct_conv3.argtypes = [i32, i32, i32, vp, vp, i32, vp, vp, i32, fl, vp, i32,
@@ -643,3 +646,67 @@ def probe_lds(n_blocks: int, iters: int, out: torch.Tensor):
         raise ValueError("out too small")
     _check(_lib.cbct_probe_lds(int(n_blocks), int(iters), _f32(out, "out"),
                                _stream(out.device)), "cbct_probe_lds")
+
+
+# ---- scatter simulator (cbct_scatter.h) --------------------------------------
+
+class _Xs(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int), ("e0", ctypes.c_double), ("de", ctypes.c_double),
+                ("mu", ctypes.c_void_p), ("J", ctypes.c_int), ("icdf", ctypes.c_void_p),
+                ("I", ctypes.c_int), ("dens", ctypes.c_void_p)]
+
+
+class ScatterTables:
+    """Cross-section tables of the scatter model, uploaded once (cbct_xs):
+    xs = dict(e0, de, mu [2, 3, K], icdf [2, 2, K, J], dens [2, 2, K, I])."""
+
+    def __init__(self, xs: dict, device="cuda"):
+        import numpy as np
+        f = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=device).contiguous()
+        self.mu, self.icdf, self.dens = f(xs["mu"]), f(xs["icdf"]), f(xs["dens"])
+        K = self.mu.shape[-1]
+        if self.mu.shape != (2, 3, K) or self.icdf.shape[:3] != (2, 2, K) or \
+                self.dens.shape[:3] != (2, 2, K):
+            raise ValueError("scatter tables have the wrong shapes")
+        self.s = _Xs(K, float(xs["e0"]), float(xs["de"]), self.mu.data_ptr(),
+                     self.icdf.shape[3], self.icdf.data_ptr(), self.dens.shape[3],
+                     self.dens.data_ptr())
+
+
+def scatter_paths(geom: Geometry, rho: torch.Tensor, xs: ScatterTables, angle: int,
+                  src: torch.Tensor, qmc: torch.Tensor, n_scatter: int,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """SamplePath (Alg. 2): records [N, n_scatter + 1, 8] of the photons src
+    [N, 4] with quasi-random points qmc [N, 5 n_scatter + 1] at projection
+    `angle`; rho = [2, nz, ny, nx] water and bone densities."""
+    if tuple(rho.shape) != (2,) + geom.vol_shape:
+        raise ValueError("rho must be [2, nz, ny, nx]")
+    N = src.shape[0]
+    if tuple(src.shape) != (N, 4) or tuple(qmc.shape) != (N, 5 * n_scatter + 1):
+        raise ValueError("src must be [N, 4] and qmc [N, 5 n + 1]")
+    if out is None:
+        out = torch.empty((N, n_scatter + 1, 8), dtype=torch.float32, device=src.device)
+    with torch.cuda.device(geom.device):
+        _check(_lib.cbct_scatter_paths(geom.handle, _f32(rho, "rho"), ctypes.byref(xs.s),
+                                       int(angle), N, _f32(src, "src"), _f32(qmc, "qmc"),
+                                       int(n_scatter), _f32(out, "rec"), _stream(geom.device)),
+               "cbct_scatter_paths")
+    return out
+
+
+def scatter_integrate(geom: Geometry, rho: torch.Tensor, xs: ScatterTables, angle: int,
+                      rec: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Integrate (Alg. 3): the scatter image [nv, nu] of the records rec
+    [..., 8] on geom's panel at projection `angle` (before I_Sigma / |Src|)."""
+    if tuple(rho.shape) != (2,) + geom.vol_shape:
+        raise ValueError("rho must be [2, nz, ny, nx]")
+    if rec.shape[-1] != 8:
+        raise ValueError("records have 8 values")
+    if out is None:
+        out = torch.empty(geom.sino_shape[1:], dtype=torch.float32, device=rec.device)
+    with torch.cuda.device(geom.device):
+        _check(_lib.cbct_scatter_integrate(geom.handle, _f32(rho, "rho"), ctypes.byref(xs.s),
+                                           int(angle), rec.numel() // 8, _f32(rec, "rec"),
+                                           _f32(out, "out"), _stream(geom.device)),
+               "cbct_scatter_integrate")
+    return out
