@@ -56,7 +56,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # device copy), valid for the kernel sources whose hash it records.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "projector_c2_f32_hbm_traffic.json")
 KERNEL_SOURCES = ("cbct_adjoint.hip", "cbct_forward.hip", "cbct_internal.h", "cbct_storage.h",
-                  "cbct_plan.cpp", "cbct_geom.cpp", "cbct_api.cpp")
+                  "cbct_plan.cpp", "cbct_geom.cpp", "cbct_api.cpp", "cbct_scratch.cpp")
+# The adjoint operator is two launches: the ds_weight pre-pass (projection
+# values times each ray's length per plane) and the gather adjoint_brick.
 
 
 def algorithmic_bytes(g):
@@ -102,6 +104,7 @@ def record_traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
                 name = r["Kernel_Name"]
                 key = ("copy" if "copyBuffer" in name else
                        "adjoint" if "adjoint_brick" in name else
+                       "adjoint_pre" if "ds_weight" in name else
                        "forward" if "forward_sweep" in name else None)
                 if key == "copy":
                     if int(r["Grid_Size"]) >= 4096:   # not the small staging copies
@@ -120,11 +123,14 @@ def record_traffic(fetch_csv, write_csv, fetch_cmd, write_cmd):
            "command_write": write_cmd, "copy_bytes": copy_kib * 1024,
            "copy_fetch_kib": fe["copy"], "copy_write_kib": wr["copy"],
            "fetch_factor": round(ff, 5), "write_factor": round(fw, 5), "kernels": {}}
-    for k in ("adjoint", "forward"):
+    for k in ("adjoint", "adjoint_pre", "forward"):
         f_kib = sum(fe[k]) / len(fe[k]) * ff
         w_kib = sum(wr[k]) / len(wr[k]) * fw
         rec["kernels"][k] = {"fetch_kib": fe[k], "write_kib": wr[k],
                              "traffic_bytes": int(round((f_kib + w_kib) * 1024))}
+    # the operator's traffic: pre-pass and gather together
+    rec["kernels"]["adjoint_operator"] = {"traffic_bytes": rec["kernels"]["adjoint"]["traffic_bytes"]
+                                          + rec["kernels"]["adjoint_pre"]["traffic_bytes"]}
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     return rec
@@ -627,12 +633,13 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": dom,
+            # the adjoint is timed as its two launches, pre-pass and gather
+            "kernel": "adjoint (ds_weight + adjoint_brick)" if dom == "adjoint" else dom,
             "achieved": round(achieved, 3),
             "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "TOP/s",
             "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": measured_traffic(dom),
+            "traffic": measured_traffic("adjoint_operator" if dom == "adjoint" else dom),
             "algorithmic_bytes": algorithmic_bytes(g),
         },
         # (counter runs with --copy-calibration leave out the bandwidth copies,

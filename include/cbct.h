@@ -134,6 +134,13 @@ cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,
  * up to FP32 rounding of the sums.  Geometries whose panel windows exceed
  * 64 KB of LDS even for 8 x 7 x 4 voxel bricks run a one-thread-per-voxel
  * kernel with the same weights (slower).
+ * The bricked kernel first writes the projections times each ray's length
+ * per plane (FP32, C x n_angles*nv*nu values) into a device buffer the
+ * library owns, one per device, kept until the process ends and grown when
+ * a call needs more: the first call on a device, and any larger one,
+ * allocates (so it must not be the one captured into a graph).  Calls on
+ * different streams are ordered on that buffer (each waits for the previous
+ * call's work); allocation failure returns CBCT_E_HIP.
  */
 cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
                          void *vol, cbct_dtype vt, int n_channels, void *stream);
@@ -147,7 +154,8 @@ cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
 cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,
                                void *const *sinos, cbct_dtype vt, cbct_dtype st, void *stream);
 
-/* Batched adjoint, the counterpart of cbct_batch_forward. */
+/* Batched adjoint, the counterpart of cbct_batch_forward (it uses the same
+ * library-owned buffer as cbct_adjoint, sized for all cases together). */
 cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, const void *const *sinos,
                                void *const *vols, cbct_dtype st, cbct_dtype vt, void *stream);
 

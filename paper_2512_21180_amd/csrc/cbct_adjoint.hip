@@ -241,9 +241,8 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&lo)[2][
 // the one below, on each axis) are added in a fixed order through LDS.
 // `lds` holds the panel window, column-major ([W][HS], HS = 2 mod 4, which
 // suits the gather's reads), and the column table; then the exchange.
-template <class SS, class VS, int KV>
-__device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
-                                             const typename SS::T *ys,
+template <class VS, int KV>
+__device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const float *ws,
                                              typename VS::T *vol, float *lds)
 {
     constexpr int kBK = 4 * KV;
@@ -316,37 +315,32 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b,
         // Columns on lanes, rows on waves (stride 4).  The loads of kSB rows
         // are issued before any of them is used, so their latencies overlap
         // instead of adding up row after row.
+        const float *proj = ws + (size_t)a * g.nv * g.nu;   // this projection, ds-weighted
         for (int uu = lane; uu < Wc; uu += 64) {
-            const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
-            if (w == 0)
+            if (w == 0) {   // uniform: one wave writes the column table
+                const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
                 cr[uu] = make_float4(col.pb, col.ps, col.t0, col.tau);
-            // 32-bit offsets within this projection (nv nu < 2^24 words)
-            const size_t pa = (size_t)a * g.nv * g.nu;
+            }
             const int u = U0 + uu;
             float *dst = yt + (size_t)uu * HS;
             for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
-                // Raw stored values, widened at the LDS store.  Rows past V1
-                // (stored as zeros) load row V1 instead, so no load sits
-                // behind a branch that would make it wait for its value.
-                typename SS::Raw val[kSB];
-                float vsq[kSB];
+                // rows past V1 (stored as zeros) load row V1 instead, so no
+                // load sits behind a branch that would make it wait for its
+                // value; 32-bit offsets within the projection (nv nu < 2^24)
+                float val[kSB];
                 bool live[kSB];
 #pragma unroll
                 for (int jj = 0; jj < kSB; ++jj) {
                     const int v = V0 + vv0 + 4 * jj;
                     live[jj] = v <= V1;
                     const int vr = min(v, V1);
-                    const size_t off = pa + (size_t)(__mul24(vr, g.nu) + u);
-                    val[jj] = SS::raw(ys, off);
-                    vsq[jj] = g.rows[vr].y;
+                    val[jj] = proj[(uint32_t)(__mul24(vr, g.nu) + u)];
                 }
 #pragma unroll
                 for (int jj = 0; jj < kSB; ++jj) {
                     const int vv = vv0 + 4 * jj;
-                    if (vv < Hs) {
-                        const float ds = ray_ds(col.dsf, col.n2, vsq[jj]);
-                        dst[vv] = live[jj] ? SS::wide(val[jj]) * ds : 0.0f;
-                    }
+                    if (vv < Hs)
+                        dst[vv] = live[jj] ? val[jj] : 0.0f;
                 }
             }
         }
@@ -443,10 +437,9 @@ __host__ __device__ inline int slots_per_xcd(const BrickArgs &A)
     return A.nbx * A.nbz * ((A.nby + 7) / 8);
 }
 
-template <class SS, class VS, int KV>
+template <class VS, int KV>
 __global__ void __launch_bounds__(kThreads)
-adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
-              typename VS::T *__restrict__ vol)
+adjoint_brick(BrickArgs A, const float *__restrict__ ws, typename VS::T *__restrict__ vol)
 {
     extern __shared__ float lds[];
     const int b = brick_of_slot(A, blockIdx.x & 7, blockIdx.x >> 3);
@@ -455,14 +448,34 @@ adjoint_brick(BrickArgs A, const typename SS::T *__restrict__ sino,
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
-    gather_brick<SS, VS, KV>(A, b, sino + ch * nsino, vol + ch * nvox, lds);
+    gather_brick<VS, KV>(A, b, ws + ch * nsino, vol + ch * nvox, lds);
+}
+
+// The ds-weighted copy of a sinogram that the bricks stage from:
+// out = y ds(a, u, v) in FP32 (ds by ray_ds, the forward's ray length per
+// plane), so that the ray length is computed once per element instead of
+// once per brick that stages it.  One workgroup per panel row of one angle
+// and channel.
+template <class SS>
+__global__ void __launch_bounds__(kThreads)
+ds_weight(DevGeom g, const typename SS::T *__restrict__ y, float *__restrict__ out)
+{
+    const int row = blockIdx.x;   // a * nv + v
+    const int a = row / g.nv, v = row - a * g.nv;
+    const size_t base = ((size_t)blockIdx.y * g.n_angles * g.nv + row) * g.nu;
+    const float v2 = g.rows[v].y;
+    const ColRec *cols = g.cols + (size_t)a * g.nu;
+    for (int u = threadIdx.x; u < g.nu; u += kThreads) {
+        const ColRec c = cols[u];
+        out[base + u] = SS::wide(SS::raw(y, base + u)) * ray_ds(c.dsf, c.n2, v2);
+    }
 }
 
 // ---- batched adjoint: one launch over all (case, brick) items ---------------
 
 struct AdjCase {
     BrickArgs A;
-    const void *sino;
+    const float *ws;   // the case's ds-weighted sinogram
     void *vol;
 };
 
@@ -472,7 +485,7 @@ struct BatchAdjArgs {
     AdjCase c[kMaxBatch];
 };
 
-template <class SS, class VS>
+template <class VS>
 __global__ void __launch_bounds__(kThreads)
 adjoint_batch(BatchAdjArgs B)
 {
@@ -487,12 +500,11 @@ adjoint_batch(BatchAdjArgs B)
     const int b = brick_of_slot(C.A, xc, li - B.first[cs]);
     if (b < 0)
         return;
-    const auto *ys = (const typename SS::T *)C.sino;
     auto *vs = (typename VS::T *)C.vol;
     switch (C.A.KV) {   // uniform over the workgroup
-    case 4: gather_brick<SS, VS, 4>(C.A, b, ys, vs, lds); break;
-    case 2: gather_brick<SS, VS, 2>(C.A, b, ys, vs, lds); break;
-    default: gather_brick<SS, VS, 1>(C.A, b, ys, vs, lds); break;
+    case 4: gather_brick<VS, 4>(C.A, b, C.ws, vs, lds); break;
+    case 2: gather_brick<VS, 2>(C.A, b, C.ws, vs, lds); break;
+    default: gather_brick<VS, 1>(C.A, b, C.ws, vs, lds); break;
     }
 }
 
@@ -515,26 +527,45 @@ static size_t brick_lds(const AdjPlan &p)
     return std::max(window, exchange) * sizeof(float);
 }
 
+static hipError_t launch_ds_weight(const DevGeom &g, const void *sino, cbct_dtype st, float *ws,
+                                   int channels, hipStream_t s)
+{
+    dim3 grid((unsigned)(g.n_angles * g.nv), channels), block(kThreads);
+    // the volume type plays no part here: dispatch on (F32, st)
+    return dispatch_storage(CBCT_F32, st, [&](auto, auto ss) -> hipError_t {
+        using SS = decltype(ss);
+        hipLaunchKernelGGL((ds_weight<SS>), grid, block, 0, s, g, (const typename SS::T *)sino, ws);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *sino,
                                 cbct_dtype st, void *vol, cbct_dtype vt, int channels,
                                 hipStream_t s)
 {
     BrickArgs A = brick_args(g, p);
     dim3 grid(8 * slots_per_xcd(A), channels), block(kThreads);
-    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
-        using VS = decltype(vs);
-        using SS = decltype(ss);
-        const size_t lds = brick_lds(p);
-        const auto *y = (const typename SS::T *)sino;
-        auto *x = (typename VS::T *)vol;
-        if (p.KV == 4)
-            hipLaunchKernelGGL((adjoint_brick<SS, VS, 4>), grid, block, lds, s, A, y, x);
-        else if (p.KV == 2)
-            hipLaunchKernelGGL((adjoint_brick<SS, VS, 2>), grid, block, lds, s, A, y, x);
-        else
-            hipLaunchKernelGGL((adjoint_brick<SS, VS, 1>), grid, block, lds, s, A, y, x);
-        return hipGetLastError();
-    });
+    const size_t nsino = (size_t)g.n_angles * g.nv * g.nu;
+    ScratchLease lease;
+    hipError_t e = scratch_acquire(nsino * channels * sizeof(float), s, lease);
+    if (e == hipSuccess)
+        e = launch_ds_weight(g, sino, st, (float *)lease.ptr, channels, s);
+    if (e == hipSuccess)
+        e = dispatch_storage(vt, st, [&](auto vs, auto) -> hipError_t {
+            using VS = decltype(vs);
+            const size_t lds = brick_lds(p);
+            const float *w = (const float *)lease.ptr;
+            auto *x = (typename VS::T *)vol;
+            if (p.KV == 4)
+                hipLaunchKernelGGL((adjoint_brick<VS, 4>), grid, block, lds, s, A, w, x);
+            else if (p.KV == 2)
+                hipLaunchKernelGGL((adjoint_brick<VS, 2>), grid, block, lds, s, A, w, x);
+            else
+                hipLaunchKernelGGL((adjoint_brick<VS, 1>), grid, block, lds, s, A, w, x);
+            return hipGetLastError();
+        });
+    const hipError_t r = scratch_release(s, lease);
+    return e != hipSuccess ? e : r;
 }
 
 hipError_t launch_adjoint_batch(int n, const cbct_geom *const *gs, const void *const *sinos,
@@ -542,24 +573,35 @@ hipError_t launch_adjoint_batch(int n, const cbct_geom *const *gs, const void *c
 {
     BatchAdjArgs B{};
     B.n_cases = n;
-    size_t lds = 0;
+    size_t lds = 0, total = 0;
     int items = 0;
+    size_t off[kMaxBatch];
     for (int i = 0; i < n; ++i) {
         const cbct_geom *g = gs[i];
         B.first[i] = items;
-        B.c[i] = AdjCase{brick_args(g->dev, g->adj), sinos[i], vols[i]};
+        B.c[i] = AdjCase{brick_args(g->dev, g->adj), nullptr, vols[i]};
         items += slots_per_xcd(B.c[i].A);
         lds = std::max(lds, brick_lds(g->adj));
+        off[i] = total;
+        total += (size_t)g->dev.n_angles * g->dev.nv * g->dev.nu;
     }
     B.first[n] = items;
     B.n_items = items;
     const int grid = 8 * items;
-    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
-        using VS = decltype(vs);
-        using SS = decltype(ss);
-        hipLaunchKernelGGL((adjoint_batch<SS, VS>), dim3(grid), dim3(kThreads), lds, s, B);
-        return hipGetLastError();
-    });
+    ScratchLease lease;
+    hipError_t e = scratch_acquire(total * sizeof(float), s, lease);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        B.c[i].ws = (const float *)lease.ptr + off[i];
+        e = launch_ds_weight(gs[i]->dev, sinos[i], st, (float *)lease.ptr + off[i], 1, s);
+    }
+    if (e == hipSuccess)
+        e = dispatch_storage(vt, st, [&](auto vs, auto) -> hipError_t {
+            using VS = decltype(vs);
+            hipLaunchKernelGGL((adjoint_batch<VS>), dim3(grid), dim3(kThreads), lds, s, B);
+            return hipGetLastError();
+        });
+    const hipError_t r = scratch_release(s, lease);
+    return e != hipSuccess ? e : r;
 }
 
 }  // namespace cbct

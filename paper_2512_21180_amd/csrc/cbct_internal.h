@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "cbct.h"
@@ -178,6 +179,21 @@ inline Col64 col_consts64(const cbct_geom_desc &d, double c, double s, int iu)
     r.ps = r.tau * dq / vq;
     return r;
 }
+
+// Library-owned device scratch (cbct_scratch.cpp): one buffer per device,
+// grown on demand.  scratch_acquire locks the device's buffer, makes stream s
+// wait for the previous user's work and returns the buffer in lease.ptr;
+// after enqueueing its work on s the caller must call scratch_release, which
+// records the completion event and unlocks.  Calls on different streams are
+// thereby ordered on the buffer; the first call (and any that needs a larger
+// buffer) allocates, so it must not run under stream capture.
+struct ScratchLease {
+    void *ptr = nullptr;
+    int device = -1;
+    std::unique_lock<std::mutex> lock;
+};
+hipError_t scratch_acquire(size_t bytes, hipStream_t s, ScratchLease &lease);
+hipError_t scratch_release(hipStream_t s, ScratchLease &lease);
 
 // Plans (cbct_plan.cpp): host FP64 analysis of tile boxes and brick
 // footprints; fills g->tiles, g->fwd and g->adj (no device work).
