@@ -523,6 +523,51 @@ def measure_simulators(reps=3):
     return {"poly_primary_c2": poly, "scatter_one_projection": scat}
 
 
+def measure_channels(reps=5):
+    """HIP-event times of channel stacks at the clinical geometry (FP32):
+    five single-channel forward calls against one five-channel stack (the
+    dual block's input of Alg. 1 at full resolution), through cbct_forward
+    on a [5, ...] tensor and through cbct_batch_forward on five cases of one
+    geometry (the learned net's call), and the same for 2, 3 and 4 channels;
+    likewise at the half- and quarter-resolution geometries of the net."""
+    import torch
+    from paper_2512_21180_amd import cbct
+    from paper_2512_21180_amd import workloads as W
+    from paper_2512_21180_amd.learned import scaled_geometry
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    res = {}
+    for r in (1, 2, 4):
+        g = scaled_geometry(W.C2, r)
+        geo = cbct.Geometry(g)
+        x = torch.stack([torch.tensor(W.random_volume(g, 40 + c), device="cuda")
+                         for c in range(5)]).float()
+        y = torch.empty((5,) + geo.sino_shape, device="cuda")
+        row = {}
+        for C in (2, 3, 4, 5):
+            t1 = timed(lambda: [cbct.forward(geo, x[c], out=y[c]) for c in range(C)])
+            ts = timed(lambda: cbct.forward(geo, x[:C], out=y[:C]))
+            tb = timed(lambda: cbct.batch_forward([geo] * C, [x[c] for c in range(C)],
+                                                  outs=[y[c] for c in range(C)]))
+            row[f"C{C}"] = {"single_ms": round(t1 * 1e3, 3), "stack_ms": round(ts * 1e3, 3),
+                            "batch_ms": round(tb * 1e3, 3), "ratio": round(ts / t1, 3)}
+        res[f"r{r}"] = row
+        print(json.dumps({f"r{r}": row}), file=sys.stderr, flush=True)
+        del x, y
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -530,6 +575,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sims", action="store_true",
                     help="time the polychromatic primary and the scatter simulators instead")
+    ap.add_argument("--channels", action="store_true",
+                    help="time five-channel forward stacks against single channels instead")
     ap.add_argument("--convs", action="store_true",
                     help="time the learned blocks' convolution kernels at the net's grids instead")
     ap.add_argument("--peaks", action="store_true",
@@ -571,6 +618,9 @@ def main():
         return
     if args.convs:
         print(json.dumps(measure_convs()), flush=True)
+        return
+    if args.channels:
+        print(json.dumps(measure_channels()), flush=True)
         return
     if args.workload != "c2":
         print(json.dumps(secondary_workload(args.workload, args.steps, args.warmup)), flush=True)

@@ -149,7 +149,12 @@ cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
  * Batched forward over n >= 1 independent single-channel cases, each with
  * its own geometry handle and buffers (host arrays of n handles and n device
  * pointers), in one launch over all cases' work items.  Results are bitwise identical to n
- * separate cbct_forward calls.
+ * separate cbct_forward calls.  With FP32 storage, cases that share one
+ * handle (e.g. the channels of a stack, as in Alg. 1) are instead cut into
+ * groups of four or two that share each sample's geometry (packed into a
+ * library-owned device buffer first, as cbct_adjoint's, and launched
+ * separately); cbct_forward does the same for n_channels > 1.  The bits do
+ * not change.
  */
 cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,
                                void *const *sinos, cbct_dtype vt, cbct_dtype st, void *stream);

@@ -250,7 +250,10 @@ def _ptrs(ts):
 
 
 def batch_forward(geoms, vols, outs=None, out_dtype=None):
-    """One launch: sinos[i] = A_i vols[i] for heterogeneous single-channel cases."""
+    """sinos[i] = A_i vols[i] for single-channel cases: FP32 cases that share a
+    geometry object run as channel groups of four or two (the multichannel
+    kernel), the rest in one launch over all their work items (same bits
+    either way)."""
     n = len(geoms)
     assert len(vols) == n and n > 0
     for g, v in zip(geoms, vols):

@@ -3,16 +3,53 @@
 // and multi-resolution use as in Alg. 1).
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "cbct_internal.h"
 
 namespace cbct {
 
+// The next chunk of a stack with `left` channels still to project: 4
+// channels where the geometry allows them (cmax = 4), else 2, and a last
+// single channel on the single-channel kernel (5 channels: 4 + 1).
+static int chunk_size(int left, int cmax)
+{
+    return left >= 4 && cmax >= 4 ? 4 : left >= 2 ? 2 : 1;
+}
+
 hipError_t launch_forward(const cbct_geom *g, const void *vol, cbct_dtype vt, void *sino,
                           cbct_dtype st, int channels, hipStream_t s)
 {
-    if (g->fwd.ok)
+    if (!g->fwd.ok)
+        return launch_forward_simple(g->dev, vol, vt, sino, st, channels, s);
+    const int cmax = forward_mc_max_channels(g);
+    if (channels < 2 || vt != CBCT_F32 || st != CBCT_F32 || cmax < 2)
         return launch_forward_tiled(g->dev, g->fwd, vol, vt, sino, st, channels, s);
-    return launch_forward_simple(g->dev, vol, vt, sino, st, channels, s);
+    // FP32 channel stacks: chunks of up to cmax channels share each sample's
+    // geometry (bitwise the same results as one channel at a time)
+    const size_t nvox = (size_t)g->desc.nx * g->desc.ny * g->desc.nz;
+    const size_t nsino = (size_t)g->desc.n_angles * g->desc.nv * g->desc.nu;
+    const float *x = (const float *)vol;
+    float *y = (float *)sino;
+    for (int c0 = 0; c0 < channels;) {
+        const int c = chunk_size(channels - c0, cmax);
+        hipError_t e;
+        if (c == 1) {
+            e = launch_forward_tiled(g->dev, g->fwd, x + c0 * nvox, vt, y + c0 * nsino, st, 1, s);
+        } else {
+            const float *xs[kMaxMcChannels];
+            float *ys[kMaxMcChannels];
+            for (int i = 0; i < c; ++i) {
+                xs[i] = x + (c0 + i) * nvox;
+                ys[i] = y + (c0 + i) * nsino;
+            }
+            e = launch_forward_mc(1, &g, xs, ys, c, s);
+        }
+        if (e != hipSuccess)
+            return e;
+        c0 += c;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st, void *vol,
@@ -85,6 +122,64 @@ extern "C" cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_d
     return finish(launch_adjoint(g, sino, st, vol, vt, n_channels, (hipStream_t)stream));
 }
 
+// Channel groups of a batch: the cases of each geometry handle that occurs
+// more than once (tiled plan) are cut into chunks of up to the plan's
+// channel limit; chunks of two or more channels are launched through the
+// multichannel kernel, up to kMaxMcGroups chunks of one size per launch, and
+// marked done.  Single leftover cases stay for the single-channel batch.
+static hipError_t batch_forward_groups(int n, const cbct_geom *const *g,
+                                       const void *const *vols, void *const *sinos,
+                                       std::vector<char> &done, hipStream_t s)
+{
+    // pending chunks per channel count
+    const cbct_geom *gg[kMaxMcChannels + 1][kMaxMcGroups];
+    const float *xx[kMaxMcChannels + 1][kMaxMcGroups * kMaxMcChannels];
+    float *yy[kMaxMcChannels + 1][kMaxMcGroups * kMaxMcChannels];
+    int m[kMaxMcChannels + 1] = {};
+    auto flush = [&](int c) -> hipError_t {
+        hipError_t e = m[c] ? launch_forward_mc(m[c], gg[c], xx[c], yy[c], c, s) : hipSuccess;
+        m[c] = 0;
+        return e;
+    };
+    std::vector<int> idx;
+    for (int i = 0; i < n; ++i) {
+        if (done[i] || !g[i]->fwd.ok)
+            continue;
+        const int cmax = forward_mc_max_channels(g[i]);
+        idx.clear();
+        for (int j = i; j < n; ++j)
+            if (!done[j] && g[j] == g[i])
+                idx.push_back(j);
+        const int cnt = (int)idx.size();
+        if (cnt < 2 || cmax < 2)
+            continue;
+        for (int c0 = 0; c0 < cnt;) {
+            const int c = chunk_size(cnt - c0, cmax);
+            if (c >= 2) {
+                gg[c][m[c]] = g[i];
+                for (int t = 0; t < c; ++t) {
+                    const int j = idx[c0 + t];
+                    xx[c][m[c] * c + t] = (const float *)vols[j];
+                    yy[c][m[c] * c + t] = (float *)sinos[j];
+                    done[j] = 1;
+                }
+                if (++m[c] == kMaxMcGroups) {
+                    hipError_t e = flush(c);
+                    if (e != hipSuccess)
+                        return e;
+                }
+            }
+            c0 += c;
+        }
+    }
+    for (int c = 2; c <= kMaxMcChannels; ++c) {
+        hipError_t e = flush(c);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 static cbct_status check_batch(int n, const cbct_geom *const *g, const void *const *a,
                                const void *const *b, cbct_dtype t1, cbct_dtype t2)
 {
@@ -115,6 +210,14 @@ extern "C" cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, cons
     if (s != CBCT_OK)
         return s;
     hipStream_t hs = (hipStream_t)stream;
+    // FP32 cases that share a geometry handle run as channel groups of the
+    // multichannel kernel (same bits as one case at a time), the rest as below
+    std::vector<char> done(n, 0);
+    if (vt == CBCT_F32 && st == CBCT_F32) {
+        hipError_t e = batch_forward_groups(n, g, vols, sinos, done, hs);
+        if (e != hipSuccess)
+            return finish(e);
+    }
     const cbct_geom *gg[kMaxBatch];
     const void *xx[kMaxBatch];
     void *yy[kMaxBatch];
@@ -126,6 +229,8 @@ extern "C" cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, cons
     };
     for (int i = 0; i < n; ++i) {
         hipError_t e = hipSuccess;
+        if (done[i])
+            continue;
         if (!g[i]->fwd.ok) {
             e = launch_forward(g[i], vols[i], vt, sinos[i], st, 1, hs);
         } else {

@@ -1,0 +1,400 @@
+// Forward projector A over C = 2 or 4 channels that share one geometry.
+//
+// Alg. 1 (arXiv 2512.21180) applies the projector to channel stacks (the
+// dual block's input holds P applied to four primal channels and to the
+// reconstruction).  Every channel's samples sit at the same points, so the
+// geometry of a sample (the z index of the ray on the plane, its floor and
+// fraction, the LDS address) is computed once here and used for all C
+// channels; the plane boxes, their table and the staging offsets are shared
+// too.  Per channel the interpolation is the single-channel kernel's
+// (forward_sweep: same expressions, same plane order, same final ds
+// product), so each channel's result is bitwise equal to a single-channel
+// call.  FP32 storage only.
+//
+// The channels are first packed into a volume of C-float vectors per voxel
+// (into the library's scratch buffer; 2 C x 4 bytes moved per voxel): each
+// cache line a tile stages then serves every channel.  Staged from C
+// separate volumes, the tiles' lines outgrew the L2 (the clinical 5-channel
+// sweep took 2.6x the time of five single-channel calls); an extra volume
+// for a fifth (or third) channel still doubled the lines and cost more than
+// it saved, so stacks run as chunks of 4 and 2 channels (and one channel on
+// the single-channel kernel).
+//
+// LDS holds the staged boxes in the same layout (one ds_read_b128 or _b64
+// per bilinear corner).  Box rows have a compile-time stride QS and count
+// ROWS: 41 x 20 where the plan's boxes fit 39 x 19 voxels (the clinical
+// case and its coarser levels: four workgroups per CU at C = 4), else
+// 65 x 32 (any tiled plan, two channels so that a workgroup stays within
+// 64 KB of LDS).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "cbct_internal.h"
+#include "cbct_storage.h"
+
+namespace cbct {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxR = 8;        // rays per thread
+constexpr int kBoxChunk = 256;  // planes whose boxes are tabulated at a time
+static_assert(kBoxChunk == kThreads, "the box table is filled one plane per thread");
+
+template <int N> struct VecOf;
+template <> struct VecOf<2> { using T = float2; };
+template <> struct VecOf<4> { using T = float4; };
+
+__device__ __forceinline__ float comp(float2 v, int i) { return i == 0 ? v.x : v.y; }
+__device__ __forceinline__ float comp(float4 v, int i)
+{
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+template <int C, int QS, int ROWS>
+struct McLayout {
+    static_assert(C == 2 || C == 4, "2 or 4 channels");
+    static_assert(ROWS % 4 == 0, "rows are staged four waves at a time");
+    static constexpr int kSlots = ROWS / 4;
+    static constexpr int kBuf = ROWS * QS * C;            // floats per staging buffer
+    static constexpr size_t kLds = 2 * (size_t)kBuf * sizeof(float) + kBoxChunk * 16;
+    static_assert(kLds <= 64 * 1024, "one workgroup within 64 KB of LDS");
+};
+
+// A group's volume as staged: the packed copy of its C channels.
+struct McGroup {
+    DevGeom g;
+    const TileRec *tiles;
+    int R, tub, n_tiles;
+    const void *vg;      // [nz][ny][nx] vectors of C channels
+    float *sino[kMaxMcChannels];
+};
+
+constexpr int kMaxGroups = kMaxMcGroups;
+
+struct McArgs {
+    int n_groups, n_items;
+    int first[kMaxGroups + 1];   // first item of each group
+    McGroup grp[kMaxGroups];
+};
+
+template <int C, int QS, int ROWS>
+__device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T, float *lds)
+{
+    using L = McLayout<C, QS, ROWS>;
+    using V0 = typename VecOf<C>::T;
+    constexpr int kSlots = L::kSlots;
+    const DevGeom &g = M.g;
+    const int R = M.R, tub = M.tub;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int uc = lane & ((1 << tub) - 1);
+    const int row0 = ((w << (6 - tub)) + (lane >> tub)) * R;
+    const int ul = min(uc, T.nu_t - 1);
+    const ColRec c = g.cols[(size_t)T.a * g.nu + T.u0 + ul];
+
+    float kb[kMaxR], ks[kMaxR], acc[C][kMaxR];
+#pragma unroll
+    for (int r = 0; r < kMaxR; ++r) {
+        const int vr = T.v0 + min(row0 + min(r, R - 1), T.nv_t - 1);
+        const float vz = g.rows[vr].x;
+        kb[r] = fmaf(c.t0, vz, g.Kb);
+        ks[r] = c.tau * vz;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            acc[ch][r] = 0.0f;
+    }
+
+    // corner rays and plane boxes: the single-channel kernel's arithmetic
+    const ColRec cA = g.cols[(size_t)T.a * g.nu + T.u0];
+    const ColRec cB = g.cols[(size_t)T.a * g.nu + T.u0 + T.nu_t - 1];
+    const float zA = g.rows[T.v0].x, zB = g.rows[T.v0 + T.nv_t - 1].x;
+    const float kbA0 = fmaf(cA.t0, zA, g.Kb), ksA0 = cA.tau * zA;
+    const float kbA1 = fmaf(cA.t0, zB, g.Kb), ksA1 = cA.tau * zB;
+    const float kbB0 = fmaf(cB.t0, zA, g.Kb), ksB0 = cB.tau * zA;
+    const float kbB1 = fmaf(cB.t0, zB, g.Kb), ksB1 = cB.tau * zB;
+
+    const bool xp = T.cls == 0;
+    const int nq = xp ? g.ny : g.nx;
+    const int sp = xp ? 1 : g.nx;
+    const int sq = xp ? g.nx : 1;
+    const int sk = g.nx * g.ny;
+
+    struct Box {
+        int qlo, klo, qw, kw;
+    };
+    int4 *boxes = (int4 *)(lds + 2 * L::kBuf);
+    auto fill_boxes = [&](int base) {
+        const int p = base + tid;
+        if (p <= T.p_hi) {
+            const float fp = (float)p;
+            const float qa = fmaf(fp, cA.ps, cA.pb), qb = fmaf(fp, cB.ps, cB.pb);
+            const float k0 = fmaf(fp, ksA0, kbA0), k1 = fmaf(fp, ksA1, kbA1);
+            const float k2 = fmaf(fp, ksB0, kbB0), k3 = fmaf(fp, ksB1, kbB1);
+            const int qlo = (int)floorf(fminf(qa, qb)) - 1;
+            const int klo = (int)floorf(fminf(fminf(k0, k1), fminf(k2, k3))) - 1;
+            const int qw = min((int)floorf(fmaxf(qa, qb)) + 3 - qlo, QS - 1);
+            const int kw = min((int)floorf(fmaxf(fmaxf(k0, k1), fmaxf(k2, k3))) + 3 - klo, ROWS);
+            boxes[tid] = make_int4(qlo, klo, qw, kw);
+        }
+    };
+    auto box_of = [&](int p, int base) {
+        const int4 v = boxes[p - base];
+        Box b;
+        b.qlo = __builtin_amdgcn_readfirstlane(v.x);
+        b.klo = __builtin_amdgcn_readfirstlane(v.y);
+        b.qw = __builtin_amdgcn_readfirstlane(v.z);
+        b.kw = __builtin_amdgcn_readfirstlane(v.w);
+        return b;
+    };
+    // Slot s of wave w holds box row w + 4 s: one vector load per slot from
+    // the packed volume, at a 32-bit byte offset (16 bytes per voxel stay
+    // under 4 GiB where this kernel runs).
+    const uint32_t step = 4u * (uint32_t)sk;
+    const V0 *vg = (const V0 *)M.vg;
+    auto fetch = [&](int p, const Box &b, V0 (&st0)[kSlots]) {
+        const int q = b.qlo + lane;
+        const bool qin = lane < b.qw && (unsigned)q < (unsigned)nq;
+        const int k0 = b.klo + w;
+        const int s_lo = k0 >= 0 ? 0 : (3 - k0) >> 2;
+        const int s_hi = min((b.kw - w + 3) >> 2, (g.nz - k0 + 3) >> 2);
+        // modular: exact whenever the slot is live; byte offsets from the
+        // (scalar) bases, so the loads take the base in scalar registers
+        const uint32_t off0 = (uint32_t)(q * sq + p * sp + k0 * sk);
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            st0[s] = V0{};
+            if (s >= s_lo && s < s_hi && qin) {
+                const uint32_t at = off0 + (uint32_t)s * step;
+                st0[s] = *(const V0 *)((const char *)vg + at * (uint32_t)sizeof(V0));
+            }
+        }
+    };
+
+    __syncthreads();   // the previous work item's readers of lds are done
+    int p = T.p_lo, base = T.p_lo;
+    fill_boxes(base);
+    __syncthreads();
+    Box nb{0, 0, 0, 0};
+    V0 stage0[kSlots];
+    if (p <= T.p_hi) {
+        nb = box_of(p, base);
+        fetch(p, nb, stage0);
+    }
+    for (; p <= T.p_hi; ++p) {
+        float *buf = lds + (p & 1) * L::kBuf;
+        V0 *P0 = (V0 *)buf;
+        const Box cb = nb;
+        if (lane < QS) {
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                if (w + 4 * s < cb.kw) {
+                    const int at = (w + 4 * s) * QS + lane;
+                    P0[at] = stage0[s];
+                }
+            }
+        }
+        __syncthreads();
+        if (p < T.p_hi) {
+            if (p + 1 - base == kBoxChunk) {
+                base += kBoxChunk;
+                fill_boxes(base);
+                __syncthreads();
+            }
+            nb = box_of(p + 1, base);
+            fetch(p + 1, nb, stage0);
+        }
+        const float fp = (float)p;
+        const float q = fmaf(fp, c.ps, c.pb);
+        const float qf = floorf(q);
+        const float wq = q - qf;
+        const int qi = (int)qf - cb.qlo;
+        const float kc = (float)cb.klo;
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r) {
+            if (r < R) {
+                const float k = fmaf(fp, ks[r], kb[r]) - kc;
+                const float kf = floorf(k);
+                const float wk = k - kf;
+                const int at = __mul24((int)kf, QS) + qi;
+                const V0 a00 = P0[at], a10 = P0[at + 1];
+                const V0 a01 = P0[at + QS], a11 = P0[at + QS + 1];
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) {
+                    const float v00 = comp(a00, ch), v10 = comp(a10, ch);
+                    const float v01 = comp(a01, ch), v11 = comp(a11, ch);
+                    const float lo = fmaf(wq, v10 - v00, v00);
+                    const float hi = fmaf(wq, v11 - v01, v01);
+                    acc[ch][r] += fmaf(wk, hi - lo, lo);
+                }
+            }
+        }
+    }
+
+    if (uc < T.nu_t) {
+        const float ds0 = c.dsf;
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r) {
+            const int vr = row0 + r;
+            if (r < R && vr < T.nv_t) {
+                const int iv = T.v0 + vr;
+                const float ds = ray_ds(ds0, c.n2, g.rows[iv].y);
+                const size_t at = ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + uc;
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    M.sino[ch][at] = acc[ch][r] * ds;
+            }
+        }
+    }
+}
+
+// One launch over the (group, tile) items of up to kMaxGroups groups, one
+// item per workgroup in XCD-contiguous order (as the single-channel batch).
+// Up to four waves per SIMD (at most 128 VGPRs) for four channels or the
+// 65 x 32 boxes, five for two channels in 41 x 20 boxes (as the
+// single-channel sweep).
+template <int C, int QS, int ROWS>
+__global__ void __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(1, C == 2 && QS == 41 ? 5 : 4)))
+forward_mc(McArgs B)
+{
+    extern __shared__ float lds[];
+    const int per = gridDim.x >> 3;
+    const int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (item >= B.n_items)
+        return;
+    int gi = 0;
+    while (gi + 1 < B.n_groups && item >= B.first[gi + 1])
+        ++gi;
+    const McGroup &M = B.grp[gi];
+    const TileRec T = M.tiles[item - B.first[gi]];
+    if (T.nu_t == 0)
+        return;
+    sweep_tile_mc<C, QS, ROWS>(M, T, lds);
+}
+
+// Pack one group's C channel-first volumes into a volume of C-float vectors.
+struct PackArgs {
+    size_t n;
+    const float *in[kMaxMcChannels];
+    void *out;
+};
+
+template <int C>
+__global__ void __launch_bounds__(kThreads) pack_channels(PackArgs P)
+{
+    using V = typename VecOf<C>::T;
+    const size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= P.n)
+        return;
+    V o;
+    if constexpr (C == 4)
+        o = make_float4(P.in[0][i], P.in[1][i], P.in[2][i], P.in[3][i]);
+    else
+        o = make_float2(P.in[0][i], P.in[1][i]);
+    ((V *)P.out)[i] = o;
+}
+
+template <int C, int QS, int ROWS>
+hipError_t launch_mc(const McArgs &B, hipStream_t s)
+{
+    using L = McLayout<C, QS, ROWS>;
+    const int grid = (B.n_items + 7) / 8 * 8;
+    hipLaunchKernelGGL((forward_mc<C, QS, ROWS>), dim3(grid), dim3(kThreads), L::kLds, s, B);
+    return hipGetLastError();
+}
+
+template <int C>
+hipError_t launch_mc_layout(const McArgs &B, bool small, hipStream_t s)
+{
+    if constexpr (C == 2)
+        return small ? launch_mc<2, 41, 20>(B, s) : launch_mc<2, 65, 32>(B, s);
+    else
+        return launch_mc<4, 41, 20>(B, s);
+}
+
+// The plan's box extents bound the kernel's FP32 boxes up to one voxel of
+// rounding per axis; the 41 x 20 layout keeps that voxel in reserve (boxes
+// of at most 39 x 19 voxels in the plan; a host test checks the FP32 boxes).
+bool small_layout(const FwdPlan &p) { return p.BQ <= 39 && p.BK <= 19; }
+
+// Fill the groups' tile records and output pointers (B.grp[i].vg is set)
+// and launch the sweep over all groups' tiles.
+hipError_t launch_mc_groups(McArgs &B, const cbct_geom *const *gs, float *const *sinos, int C,
+                            int n, hipStream_t s)
+{
+    bool small = true;
+    int items = 0;
+    for (int i = 0; i < n; ++i) {
+        const cbct_geom *g = gs[i];
+        small = small && small_layout(g->fwd);
+        B.first[i] = items;
+        McGroup &M = B.grp[i];
+        M.g = g->dev;
+        M.tiles = g->fwd.tiles;
+        M.R = g->fwd.R;
+        M.tub = g->fwd.TU == 32 ? 5 : 6;
+        M.n_tiles = g->fwd.n_tiles;
+        for (int ch = 0; ch < C; ++ch)
+            M.sino[ch] = sinos[(size_t)i * C + ch];
+        items += g->fwd.n_tiles;
+    }
+    B.first[n] = items;
+    B.n_items = items;
+    return C == 4 ? launch_mc_layout<4>(B, small, s) : launch_mc_layout<2>(B, small, s);
+}
+
+}  // namespace
+
+int forward_mc_max_channels(const cbct_geom *g)
+{
+    const FwdPlan &p = g->fwd;
+    const uint64_t nvox = (uint64_t)g->desc.nx * g->desc.ny * g->desc.nz;
+    if (!p.ok || p.BQ > 64 || p.BK > 32 || nvox * 16 >= (1ull << 32))
+        return 0;
+    return small_layout(p) ? 4 : 2;
+}
+
+// Packs every group's channels into the library's scratch buffer (held
+// until the sweep is enqueued), then launches the sweep.
+hipError_t launch_forward_mc(int n, const cbct_geom *const *gs, const float *const *vols,
+                             float *const *sinos, int C, hipStream_t s)
+{
+    if (n < 1 || n > kMaxGroups || (C != 2 && C != 4))
+        return hipErrorInvalidValue;
+    size_t off[kMaxGroups + 1] = {0};
+    for (int i = 0; i < n; ++i) {
+        const cbct_geom *g = gs[i];
+        if (forward_mc_max_channels(g) < C)
+            return hipErrorInvalidValue;   // 65 x 32 boxes of 4 channels exceed 64 KB of LDS
+        const size_t nvox = (size_t)g->desc.nx * g->desc.ny * g->desc.nz;
+        off[i + 1] = off[i] + (nvox * C * sizeof(float) + 255) / 256 * 256;
+    }
+    McArgs B{};
+    B.n_groups = n;
+    ScratchLease lease;
+    hipError_t e = scratch_acquire(off[n], s, lease);
+    if (e == hipSuccess) {
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            const cbct_geom *g = gs[i];
+            PackArgs P{};
+            P.n = (size_t)g->desc.nx * g->desc.ny * g->desc.nz;
+            for (int ch = 0; ch < C; ++ch)
+                P.in[ch] = vols[(size_t)i * C + ch];
+            P.out = (char *)lease.ptr + off[i];
+            const dim3 grid((unsigned)((P.n + kThreads - 1) / kThreads));
+            if (C == 4)
+                hipLaunchKernelGGL(pack_channels<4>, grid, dim3(kThreads), 0, s, P);
+            else
+                hipLaunchKernelGGL(pack_channels<2>, grid, dim3(kThreads), 0, s, P);
+            e = hipGetLastError();
+            B.grp[i].vg = P.out;
+        }
+        if (e == hipSuccess)
+            e = launch_mc_groups(B, gs, sinos, C, n, s);
+    }
+    const hipError_t r = scratch_release(s, lease);
+    return e != hipSuccess ? e : r;
+}
+
+}  // namespace cbct

@@ -220,6 +220,20 @@ hipError_t launch_forward_batch(int n, const cbct_geom *const *g, const void *co
 hipError_t launch_adjoint_batch(int n, const cbct_geom *const *g, const void *const *sinos,
                                 void *const *vols, cbct_dtype st, cbct_dtype vt, hipStream_t s);
 
+// Multichannel forward (cbct_forward_mc.hip): n groups of C = 2 or 4
+// channels, each group one geometry with a tiled plan; vols and sinos hold
+// n * C FP32 pointers, group-major.  The channels are first packed (vectors
+// of C channels per voxel) into the library's scratch buffer.  Every
+// channel's output is bitwise equal to the single-channel tiled kernel's.
+// The largest C a geometry allows: 4 where its boxes fit 39 x 19 voxels
+// (staged in 41 x 20 LDS rows), else 2 (65 x 32), 0 where the plan is not
+// tiled or 16 bytes per voxel reach 4 GiB.
+constexpr int kMaxMcChannels = 4;
+constexpr int kMaxMcGroups = 8;
+int forward_mc_max_channels(const cbct_geom *g);
+hipError_t launch_forward_mc(int n, const cbct_geom *const *g, const float *const *vols,
+                             float *const *sinos, int C, hipStream_t s);
+
 // Dispatch to the tiled kernels when the plan allows, else the simple ones.
 hipError_t launch_forward(const cbct_geom *g, const void *vol, cbct_dtype vt, void *sino,
                           cbct_dtype st, int channels, hipStream_t s);

@@ -1,8 +1,14 @@
-"""Single-scale learned primal-dual reconstruction on the library's kernels.
+"""Learned primal-dual reconstruction (multiscale) on the library's kernels.
 
-arXiv 2512.21180, Alg. 1, at one resolution and with n unrolled iterations:
-primal latent f (8 volumes), dual latent h (8 sinograms), reconstruction x,
-normalised operators A / L (L = ||A||_2) and normalised data y.  Iteration i:
+arXiv 2512.21180, Alg. 1, with n unrolled iterations: primal latent f (8
+volumes), dual latent h (8 sinograms), reconstruction x, normalised
+operators A / L (L = ||A||_2) and normalised data y.  Iteration i runs at
+resolution 1/r_i (r_i in {1, 2, 4}, non-increasing; all 1 gives the
+single-resolution net): the operator is the projector of the geometry with
+r_i-times coarser voxels, pixels and angle step (P_alpha), the data and the
+field of view are pooled to it (ProjDown, Downsample), and the latents and
+x are carried to the next iteration's resolution by nearest upsampling.
+At one resolution iteration i reads:
 
     d1, d2 = halves of h;   p1, p2 = halves of f
     d2 <- d2 + Gamma_i([A p2 / L, A x / L, d1, y])           10 -> 4 channels
@@ -206,7 +212,7 @@ class LearnedPD:
             Vr = self.V if r == 1 else cbct.pool(self.V, r)
             self.levels[r] = {"geo": gr, "V": Vr, "vgrid": tuple(gr.vol_shape),
                               "sgrid": tuple(gr.sino_shape), "bufs": {}}
-        # kept for callers of the single-scale interface
+        # full-resolution grids (the output resolution)
         self.vgrid = tuple(geo.vol_shape)
         self.sgrid = tuple(geo.sino_shape)
 

@@ -1,4 +1,4 @@
-"""Train the single-scale learned primal-dual net on projector-simulated data.
+"""Train the learned primal-dual net (any scales) on projector-simulated data.
 
 Training pairs: seeded ellipsoid phantoms in a 300 mm body cylinder (the
 clinical-size recipe), Poisson noise at I0 photons per pixel on the library's

@@ -138,9 +138,10 @@ def test_sample_count_matches_oracle(oracle, hosts, name):
     assert hosts[name].sample_count() == oracle.sample_count(GEOMS[name])
 
 
-def _fwd_tile_check(h, T):
+def _fwd_tile_check(h, T, q_lim=64, k_lim=32):
     """Emulate the forward kernel's per-plane box (FP32): staged columns
-    [qlo, qlo + qw), rows [klo, klo + kw), qw <= 64, kw <= 32; every bilinear
+    [qlo, qlo + qw), rows [klo, klo + kw), qw <= q_lim, kw <= k_lim (64 x 32,
+    or 40 x 20 for the multichannel kernel's small layout); every bilinear
     read (q0, q0 + 1) x (k0, k0 + 1) of every ray must fall inside."""
     a, cls, u0, nu_t, v0, nv_t, p_lo, p_hi = [int(x) for x in T]
     if nu_t == 0 or p_lo > p_hi:
@@ -158,7 +159,7 @@ def _fwd_tile_check(h, T):
     kmax = np.maximum(np.maximum(ks[0], ks[1]), np.maximum(ks[2], ks[3]))
     klo = np.floor(kmin) - 1
     kw = np.floor(kmax) + 3 - klo
-    assert qw.max() <= 64 and kw.max() <= 32, (T, qw.max(), kw.max())
+    assert qw.max() <= q_lim and kw.max() <= k_lim, (T, qw.max(), kw.max())
     q = fma32(p, C[None, :, 1, None], C[None, :, 0, None])                 # [P, U, 1]
     kb = fma32(C[:, 2, None], Vz[None, :], Kb)                              # [U, V]
     kss = (C[:, 3, None] * Vz[None, :]).astype(np.float32)
@@ -172,9 +173,12 @@ def _fwd_tile_check(h, T):
 
 @pytest.mark.parametrize("name", sorted(GEOMS))
 def test_forward_box_indices_stay_in_lds(hosts, name):
-    h = hosts[name]
+    _check_boxes(hosts[name], 64, 32)
+
+
+def _check_boxes(h, q_lim, k_lim):
     assert h.info[0] == 1, "tiled forward expected"
-    assert h.info[2] <= 64 and h.info[3] <= 32
+    assert h.info[2] <= q_lim and h.info[3] <= k_lim
     tiles = h.tiles
     if len(tiles) > 1500:
         rng = W.rng(11)
@@ -184,8 +188,30 @@ def test_forward_box_indices_stay_in_lds(hosts, name):
         diag = np.argsort(np.abs(np.abs(np.sin(2 * ang)) - 1))[:2]
         pick = np.union1d(pick, np.nonzero(np.isin(tiles[:, 0], diag))[0])
         tiles = tiles[pick]
-    n = sum(_fwd_tile_check(h, T) for T in tiles)
+    n = sum(_fwd_tile_check(h, T, q_lim, k_lim) for T in tiles)
     assert n > 0
+
+
+def test_multichannel_small_layout_boxes():
+    """The multichannel forward stages boxes in 41 x 20 LDS rows where the
+    plan's box extents are at most 39 x 19 voxels (one voxel of FP32
+    rounding in reserve per axis): on every such geometry here (the clinical
+    case, its half- and quarter-resolution levels, a 3 mm case and the GPU
+    tests' small cases), every FP32 box fits 40 x 20 and every read falls
+    inside it."""
+    from paper_2512_21180_amd.learned import scaled_geometry
+    cases = [W.C2, scaled_geometry(W.C2, 2), scaled_geometry(W.C2, 4), W.c3_geometries()[10],
+             RAGGED, W.cropped(W.C2, n_angles=24, nu=160, nv=96, n=64)]
+    n_small = 0
+    for g in cases:
+        h = Host(g)
+        try:
+            if h.info[2] <= 39 and h.info[3] <= 19:
+                n_small += 1
+                _check_boxes(h, 40, 20)
+        finally:
+            h.close()
+    assert n_small == len(cases)
 
 
 def taps_rounded(nt):
