@@ -11,6 +11,13 @@ half of the projections), summed over all iterates (the output list I of
 Alg. 1).  Adam with linear warm-up and cosine decay.  Augmentation:
 left-right and head-foot flips.
 
+Robustness: a step whose loss or any gradient is not finite is skipped
+(the run stops after --max-skips in a row); every --checkpoint-every steps
+and at the end the weights, the Adam moments and step counts, the next step
+and the sampling generator's state go to <out>.ckpt, written to a temporary
+file and renamed over the old one, and --resume <out>.ckpt continues the
+run where it stopped.
+
 The default training geometry is a 32-layer z-slab of the clinical case with
 the panel rows that see it: the same voxel and pixel pitch, angles, offset
 and magnification, so the 3x3x3 blocks learn the same local operators at a
@@ -21,6 +28,7 @@ quarter of the cost per step.
 from __future__ import annotations
 
 import argparse
+import json
 import math
 import os
 import sys
@@ -52,24 +60,66 @@ def phantom(g: dict, name: str, seed: int) -> np.ndarray:
                              W.geometry(60, 96, 96, 3.2, 3.2, 48, 48, 48, 6.0, off_u=60.0))
 
 
-def save(net: learned.PDNet, path: str, meta: dict):
+def _weights(net: learned.PDNet) -> dict:
     state = {k: v.detach().cpu() for k, v in net.state_dict().items()}
     state["perms"] = torch.tensor(net.perms, dtype=torch.int64)
     state["meta_n_iter"] = torch.tensor(net.n_iter)
     state["meta_scales"] = torch.tensor(net.scales, dtype=torch.int64)
     state["meta_fdk_init"] = torch.tensor(1 if net.init == "fdk" else 0)
-    torch.save(state, path)
+    return state
 
 
-def load(path: str, device="cuda") -> learned.PDNet:
-    state = torch.load(path, map_location="cpu", weights_only=True)
+def _write(obj, path: str):
+    """torch.save to a temporary file beside path, then rename over it: a
+    crash mid-write leaves the previous file intact."""
+    tmp = path + ".tmp"
+    torch.save(obj, tmp)
+    os.replace(tmp, path)
+
+
+def save(net: learned.PDNet, path: str, meta: dict):
+    _write(_weights(net), path)
+
+
+def _net_from(state: dict) -> learned.PDNet:
+    state = dict(state)
     n_iter = int(state.pop("meta_n_iter"))
     scales = state.pop("meta_scales").tolist() if "meta_scales" in state else None
     init = "fdk" if int(state.pop("meta_fdk_init", torch.tensor(0))) else "zero"
     net = learned.PDNet(n_iter=n_iter, scales=scales, init=init)
     net.perms = [list(map(int, r)) for r in state.pop("perms").tolist()]
     net.load_state_dict(state)
-    return net.to(device)
+    return net
+
+
+def load(path: str, device="cuda") -> learned.PDNet:
+    return _net_from(torch.load(path, map_location="cpu", weights_only=True)).to(device)
+
+
+def save_checkpoint(path: str, net: learned.PDNet, opt: torch.optim.Optimizer, step: int,
+                    rng: np.random.Generator, skipped: int):
+    """Everything a resumed run needs to continue as if uninterrupted: the
+    weights, the optimiser's moments and step counts, the next step, the
+    sampling generator's state and the count of skipped steps."""
+    _write({"net": _weights(net), "opt": opt.state_dict(), "step": int(step),
+            "rng": json.dumps(rng.bit_generator.state), "skipped": int(skipped)}, path)
+
+
+def load_checkpoint(path: str, device="cuda"):
+    """(net, optimiser state dict, next step, generator, skipped) of a checkpoint."""
+    ck = torch.load(path, map_location="cpu", weights_only=True)
+    net = _net_from(ck["net"]).to(device)
+    rng = np.random.default_rng()
+    rng.bit_generator.state = json.loads(ck["rng"])
+    return net, ck["opt"], int(ck["step"]), rng, int(ck.get("skipped", 0))
+
+
+def finite_step(loss: float, params) -> bool:
+    """True when the loss and every gradient are finite (a step with a NaN
+    or an infinity anywhere is skipped rather than taken)."""
+    if not math.isfinite(loss):
+        return False
+    return all(p.grad is None or bool(torch.isfinite(p.grad).all()) for p in params)
 
 
 def simulate_pair(geo, x_mu: torch.Tensor, I0: float, seed: int, L: float):
@@ -94,8 +144,14 @@ def main(argv=None):
     ap.add_argument("--pool", type=int, default=48, help="distinct training phantoms")
     ap.add_argument("--I0", type=float, default=1e5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--resume", default=None)
+    ap.add_argument("--resume", default=None,
+                    help="a checkpoint (<out>.ckpt: weights, optimiser, step, generator) "
+                         "or a weights file (weights only, fresh optimiser)")
     ap.add_argument("--out", required=True)
+    ap.add_argument("--checkpoint-every", type=int, default=50,
+                    help="steps between checkpoints written to <out>.ckpt")
+    ap.add_argument("--max-skips", type=int, default=20,
+                    help="consecutive non-finite steps before giving up")
     ap.add_argument("--time-limit", type=float, default=1e9, help="seconds; stop and save")
     args = ap.parse_args(argv)
     t_start = time.time()
@@ -108,10 +164,19 @@ def main(argv=None):
     wmask = (fov / fov.sum()).contiguous()
     scales = [int(v) for v in args.scales.split(",")] if args.scales else None
     n_iter = len(scales) if scales else args.n_iter
-    net = load(args.resume) if args.resume else \
-        learned.PDNet(n_iter, seed=args.seed, scales=scales, init=args.init).cuda()
+    start, skipped, opt_state = 0, 0, None
+    rng = np.random.default_rng(args.seed + 17)
+    if args.resume and args.resume.endswith(".ckpt"):
+        net, opt_state, start, rng, skipped = load_checkpoint(args.resume)
+    elif args.resume:
+        net = load(args.resume)
+    else:
+        net = learned.PDNet(n_iter, seed=args.seed, scales=scales, init=args.init).cuda()
     model = learned.LearnedPD(net, geo, V, L)
     opt = torch.optim.Adam(net.parameters(), lr=args.lr)
+    if opt_state is not None:
+        opt.load_state_dict(opt_state)
+    ckpt = args.out + ".ckpt"
     print(f"[train] geometry {args.geometry} vol {geo.vol_shape} sino {geo.sino_shape} "
           f"L {L:.5e} params {sum(p.numel() for p in net.parameters())}", flush=True)
     pool = []
@@ -120,9 +185,10 @@ def main(argv=None):
         if (k + 1) % 8 == 0:
             print(f"[train] phantoms {k + 1}/{args.pool} ({time.time() - t_start:.0f} s)",
                   flush=True)
-    rng = np.random.default_rng(args.seed + 17)
     hist = []
-    for step in range(args.steps):
+    run_of_skips = 0
+    step = start - 1
+    for step in range(start, args.steps):
         lr = args.lr * min(1.0, (step + 1) / args.warmup) * \
             0.5 * (1.0 + math.cos(math.pi * step / args.steps))
         for grp in opt.param_groups:
@@ -136,17 +202,33 @@ def main(argv=None):
         y, x_n = simulate_pair(geo, x, args.I0, seed=int(rng.integers(1 << 31)), L=L)
         opt.zero_grad(set_to_none=True)
         loss = model.loss_and_grad(y, x_n, wmask)
-        torch.nn.utils.clip_grad_norm_(net.parameters(), 1.0)
-        opt.step()
-        hist.append(loss)
-        if (step + 1) % 10 == 0 or step == 0:
-            print(f"[train] step {step + 1}/{args.steps} loss {np.mean(hist[-10:]):.5f} "
+        if finite_step(loss, net.parameters()):
+            torch.nn.utils.clip_grad_norm_(net.parameters(), 1.0)
+            opt.step()
+            hist.append(loss)
+            run_of_skips = 0
+        else:
+            skipped += 1
+            run_of_skips += 1
+            print(f"[train] step {step + 1}: non-finite loss or gradient, skipped "
+                  f"({skipped} so far)", flush=True)
+            if run_of_skips >= args.max_skips:
+                print(f"[train] {run_of_skips} non-finite steps in a row: stopping; the "
+                      f"last checkpoint is {ckpt}", flush=True)
+                return 1
+        if (step + 1) % 10 == 0 or step == start:
+            print(f"[train] step {step + 1}/{args.steps} loss "
+                  f"{np.mean(hist[-10:]) if hist else float('nan'):.5f} "
                   f"lr {lr:.2e} ({time.time() - t_start:.0f} s)", flush=True)
+        if (step + 1) % args.checkpoint_every == 0:
+            save_checkpoint(ckpt, net, opt, step + 1, rng, skipped)
         if time.time() - t_start > args.time_limit:
             print(f"[train] time limit reached at step {step + 1}", flush=True)
             break
+    save_checkpoint(ckpt, net, opt, step + 1, rng, skipped)
     save(net, args.out, {})
-    print(f"[train] saved {args.out} after {time.time() - t_start:.0f} s", flush=True)
+    print(f"[train] saved {args.out} and {ckpt} after {time.time() - t_start:.0f} s", flush=True)
+    return 0
 
 
 if __name__ == "__main__":
