@@ -602,7 +602,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on a single GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

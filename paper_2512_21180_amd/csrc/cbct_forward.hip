@@ -31,6 +31,14 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kMaxR = 8;       // rays per thread
+
+// LDS addresses as 32-bit numbers (a row address is one multiply-add).
+typedef __attribute__((address_space(3))) const float lds_float;
+__device__ inline uint32_t lds_addr(const float *p)
+{
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const float *)p;
+}
+__device__ inline lds_float *lds_ptr(uint32_t a) { return (lds_float *)(uintptr_t)a; }
 constexpr int kQS = 65;        // LDS row stride (floats): box rows are <= 64 wide
 constexpr int kMaxRows = 32;   // box rows (z) per plane
 constexpr int kSlots = kMaxRows / 4;
@@ -47,12 +55,16 @@ constexpr size_t kFwdLds = 2 * (size_t)kMaxRows * kQS * sizeof(float) + kBoxChun
 // [klo, klo + kw), from the corner rays' crossings widened by one voxel for
 // rounding; wave w stages rows w, w + 4, ... with lane l holding column l,
 // so each row is one load per lane.
-// tub: log2 of the tile width (6 or 5).
-template <class VS, class SS>
-__device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, int R, int tub,
+// tub: log2 of the tile width (6 or 5).  RC > 0 fixes R at compile time (the
+// plans' usual 8 rays per thread): the per-ray tests then vanish, which
+// matters because the sweep issues nearly as many scalar as vector
+// instructions and a SIMD takes one of each per four cycles.
+template <class VS, class SS, int RC = 0>
+__device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, int R_rt, int tub,
                            const typename VS::T *__restrict__ v,
                            typename SS::T *__restrict__ sino, float *lds)
 {
+    const int R = RC > 0 ? RC : R_rt;
     const int tid = threadIdx.x;
     // the wave index is uniform: the staging's slot ranges below are
     // scalar, so their tests are scalar branches
@@ -126,20 +138,28 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     // lane).  Offsets are 32-bit byte offsets from the volume base (the plan
     // keeps tiled volumes under 4 GiB), advanced by 4 sk per slot.
     const uint32_t step = 4u * (uint32_t)sk * (uint32_t)sizeof(typename VS::T);
+    // The live slots form a wave-uniform bit mask (one scalar bit test per
+    // slot) and the lane test is one exec region for all slots: per-slot
+    // range tests and exec juggling had made the sweep issue nearly as many
+    // scalar as vector instructions.
     auto fetch = [&](int p, const Box &b, Raw (&st)[kSlots]) {
         const int q = b.qlo + lane;
         const bool qin = lane < b.qw && (unsigned)q < (unsigned)nq;
         const int k0 = b.klo + w;
         const int s_lo = k0 >= 0 ? 0 : (3 - k0) >> 2;
         const int s_hi = min((b.kw - w + 3) >> 2, (g.nz - k0 + 3) >> 2);
+        const uint32_t live = s_hi > s_lo ? ((1u << s_hi) - 1u) & ~((1u << s_lo) - 1u) : 0u;
         // modular: exact whenever the slot is live
         const uint32_t off0 =
             (uint32_t)(q * sq + p * sp + k0 * sk) * (uint32_t)sizeof(typename VS::T);
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
+        for (int s = 0; s < kSlots; ++s)
             st[s] = Raw(0);
-            if (s >= s_lo && s < s_hi && qin)
-                st[s] = VS::raw_at(v, off0 + (uint32_t)s * step);
+        if (qin) {
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s)
+                if (live & (1u << s))
+                    st[s] = VS::raw_at(v, off0 + (uint32_t)s * step);
         }
     };
 
@@ -156,9 +176,11 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     for (; p <= T.p_hi; ++p) {
         float *buf = lds + (p & 1) * (kMaxRows * kQS);
         const Box cb = nb;
+        // the slots inside the box rows, as a wave-uniform bit mask
+        const uint32_t rows = (1u << ((cb.kw - w + 3) >> 2)) - 1u;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s)
-            if (w + 4 * s < cb.kw)
+            if (rows & (1u << s))
                 buf[(w + 4 * s) * kQS + lane] = VS::wide(stage[s]);
         __syncthreads();
         if (p < T.p_hi) {
@@ -174,15 +196,19 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
         const float q = fmaf(fp, c.ps, c.pb);
         const float qf = floorf(q);
         const float wq = q - qf;
-        const int qi = (int)qf - cb.qlo;
+        // byte address of this column's position in box row 0
+        const uint32_t colb = lds_addr(buf) + 4u * (uint32_t)((int)qf - cb.qlo);
         const float kc = (float)cb.klo;
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             if (r < R) {
+                // k >= 0 inside the box (its lowest row lies below every
+                // ray), so truncation is the floor and the fraction exact:
+                // the same values as floor and subtraction, two operations
+                // fewer with the row address in one multiply-add
                 const float k = fmaf(fp, ks[r], kb[r]) - kc;
-                const float kf = floorf(k);
-                const float wk = k - kf;
-                const float *row = buf + __mul24((int)kf, kQS) + qi;
+                const float wk = __builtin_amdgcn_fractf(k);
+                const lds_float *row = lds_ptr(__umul24((uint32_t)k, 4u * kQS) + colb);
                 const float v00 = row[0], v10 = row[1];
                 const float v01 = row[kQS], v11 = row[kQS + 1];
                 const float lo = fmaf(wq, v10 - v00, v00);
@@ -215,7 +241,7 @@ struct SweepArgs {
 // At most five waves per SIMD: with more resident tiles the planes' boxes of
 // different tiles compete for the caches (clinical case: 15.3 ms at six
 // waves, 13.5 ms at five, 14.5 ms at four).
-template <class VS, class SS>
+template <class VS, class SS, int RC>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 5)))
 forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
               typename SS::T *__restrict__ sino)
@@ -232,7 +258,7 @@ forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
-    sweep_tile<VS, SS>(A.g, T, A.R, A.tub, vol + ch * nvox, sino + ch * nsino, lds);
+    sweep_tile<VS, SS, RC>(A.g, T, A.R, A.tub, vol + ch * nvox, sino + ch * nsino, lds);
 }
 
 // ---- batched forward: one launch over all (case, tile) items ----------------
@@ -285,8 +311,12 @@ hipError_t launch_forward_tiled(const DevGeom &g, const FwdPlan &p, const void *
     return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
         using VS = decltype(vs);
         using SS = decltype(ss);
-        hipLaunchKernelGGL((forward_sweep<VS, SS>), grid, block, lds, s, A,
-                           (const typename VS::T *)vol, (typename SS::T *)sino);
+        if (p.R == kMaxR)
+            hipLaunchKernelGGL((forward_sweep<VS, SS, kMaxR>), grid, block, lds, s, A,
+                               (const typename VS::T *)vol, (typename SS::T *)sino);
+        else
+            hipLaunchKernelGGL((forward_sweep<VS, SS, 0>), grid, block, lds, s, A,
+                               (const typename VS::T *)vol, (typename SS::T *)sino);
         return hipGetLastError();
     });
 }

@@ -41,6 +41,14 @@ constexpr int kMaxR = 8;        // rays per thread
 constexpr int kBoxChunk = 256;  // planes whose boxes are tabulated at a time
 static_assert(kBoxChunk == kThreads, "the box table is filled one plane per thread");
 
+// LDS addresses as 32-bit numbers (a row address is one multiply-add).
+typedef __attribute__((address_space(3))) const float lds_float;
+__device__ inline uint32_t lds_addr(const float *p)
+{
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const float *)p;
+}
+__device__ inline lds_float *lds_ptr(uint32_t a) { return (lds_float *)(uintptr_t)a; }
+
 template <int N> struct VecOf;
 template <> struct VecOf<2> { using T = float2; };
 template <> struct VecOf<4> { using T = float4; };
@@ -78,14 +86,14 @@ struct McArgs {
     McGroup grp[kMaxGroups];
 };
 
-template <int C, int QS, int ROWS>
+template <int C, int QS, int ROWS, int RC>
 __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T, float *lds)
 {
     using L = McLayout<C, QS, ROWS>;
     using V0 = typename VecOf<C>::T;
     constexpr int kSlots = L::kSlots;
     const DevGeom &g = M.g;
-    const int R = M.R, tub = M.tub;
+    const int R = RC > 0 ? RC : M.R, tub = M.tub;   // RC: rays per thread fixed at compile time
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int uc = lane & ((1 << tub) - 1);
@@ -158,16 +166,22 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
         const int k0 = b.klo + w;
         const int s_lo = k0 >= 0 ? 0 : (3 - k0) >> 2;
         const int s_hi = min((b.kw - w + 3) >> 2, (g.nz - k0 + 3) >> 2);
+        // live slots as a wave-uniform bit mask, the lane test as one exec
+        // region (as in the single-channel sweep)
+        const uint32_t live = s_hi > s_lo ? ((1u << s_hi) - 1u) & ~((1u << s_lo) - 1u) : 0u;
         // modular: exact whenever the slot is live; byte offsets from the
         // (scalar) bases, so the loads take the base in scalar registers
         const uint32_t off0 = (uint32_t)(q * sq + p * sp + k0 * sk);
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
+        for (int s = 0; s < kSlots; ++s)
             st0[s] = V0{};
-            if (s >= s_lo && s < s_hi && qin) {
-                const uint32_t at = off0 + (uint32_t)s * step;
-                st0[s] = *(const V0 *)((const char *)vg + at * (uint32_t)sizeof(V0));
-            }
+        if (qin) {
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s)
+                if (live & (1u << s)) {
+                    const uint32_t at = off0 + (uint32_t)s * step;
+                    st0[s] = *(const V0 *)((const char *)vg + at * (uint32_t)sizeof(V0));
+                }
         }
     };
 
@@ -185,14 +199,13 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
         float *buf = lds + (p & 1) * L::kBuf;
         V0 *P0 = (V0 *)buf;
         const Box cb = nb;
+        // the slots inside the box rows, as a wave-uniform bit mask
+        const uint32_t rows = (1u << ((cb.kw - w + 3) >> 2)) - 1u;
         if (lane < QS) {
 #pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                if (w + 4 * s < cb.kw) {
-                    const int at = (w + 4 * s) * QS + lane;
-                    P0[at] = stage0[s];
-                }
-            }
+            for (int s = 0; s < kSlots; ++s)
+                if (rows & (1u << s))
+                    P0[(w + 4 * s) * QS + lane] = stage0[s];
         }
         __syncthreads();
         if (p < T.p_hi) {
@@ -208,17 +221,21 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
         const float q = fmaf(fp, c.ps, c.pb);
         const float qf = floorf(q);
         const float wq = q - qf;
-        const int qi = (int)qf - cb.qlo;
+        // byte address of this column's position in box row 0
+        const uint32_t colb = lds_addr(buf) + (uint32_t)sizeof(V0) * (uint32_t)((int)qf - cb.qlo);
         const float kc = (float)cb.klo;
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             if (r < R) {
+                // as in the single-channel sweep: k >= 0 in the box, so the
+                // truncation is the floor and the fraction exact
                 const float k = fmaf(fp, ks[r], kb[r]) - kc;
-                const float kf = floorf(k);
-                const float wk = k - kf;
-                const int at = __mul24((int)kf, QS) + qi;
-                const V0 a00 = P0[at], a10 = P0[at + 1];
-                const V0 a01 = P0[at + QS], a11 = P0[at + QS + 1];
+                const float wk = __builtin_amdgcn_fractf(k);
+                // (a generic pointer made from the LDS address: the
+                // compiler still reads it from LDS)
+                const V0 *row = (const V0 *)(lds_ptr(__umul24((uint32_t)k, (uint32_t)sizeof(V0) * QS) + colb));
+                const V0 a00 = row[0], a10 = row[1];
+                const V0 a01 = row[QS], a11 = row[QS + 1];
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch) {
                     const float v00 = comp(a00, ch), v10 = comp(a10, ch);
@@ -253,7 +270,7 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
 // Up to four waves per SIMD (at most 128 VGPRs) for four channels or the
 // 65 x 32 boxes, five for two channels in 41 x 20 boxes (as the
 // single-channel sweep).
-template <int C, int QS, int ROWS>
+template <int C, int QS, int ROWS, int RC>
 __global__ void __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(1, C == 2 && QS == 41 ? 5 : 4)))
 forward_mc(McArgs B)
@@ -270,7 +287,7 @@ forward_mc(McArgs B)
     const TileRec T = M.tiles[item - B.first[gi]];
     if (T.nu_t == 0)
         return;
-    sweep_tile_mc<C, QS, ROWS>(M, T, lds);
+    sweep_tile_mc<C, QS, ROWS, RC>(M, T, lds);
 }
 
 // Pack one group's C channel-first volumes into a volume of C-float vectors.
@@ -300,7 +317,13 @@ hipError_t launch_mc(const McArgs &B, hipStream_t s)
 {
     using L = McLayout<C, QS, ROWS>;
     const int grid = (B.n_items + 7) / 8 * 8;
-    hipLaunchKernelGGL((forward_mc<C, QS, ROWS>), dim3(grid), dim3(kThreads), L::kLds, s, B);
+    bool all8 = true;   // every group's plan takes 8 rays per thread
+    for (int i = 0; i < B.n_groups; ++i)
+        all8 = all8 && B.grp[i].R == kMaxR;
+    if (all8)
+        hipLaunchKernelGGL((forward_mc<C, QS, ROWS, kMaxR>), dim3(grid), dim3(kThreads), L::kLds, s, B);
+    else
+        hipLaunchKernelGGL((forward_mc<C, QS, ROWS, 0>), dim3(grid), dim3(kThreads), L::kLds, s, B);
     return hipGetLastError();
 }
 
