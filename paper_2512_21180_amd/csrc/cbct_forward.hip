@@ -199,6 +199,9 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
         // byte address of this column's position in box row 0
         const uint32_t colb = lds_addr(buf) + 4u * (uint32_t)((int)qf - cb.qlo);
         const float kc = (float)cb.klo;
+        // all rays' reads first, then their arithmetic: the reads of the
+        // rays overlap instead of each ray waiting for its own
+        float wk[kMaxR], v00[kMaxR], v10[kMaxR], v01[kMaxR], v11[kMaxR];
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             if (r < R) {
@@ -207,13 +210,20 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
                 // the same values as floor and subtraction, two operations
                 // fewer with the row address in one multiply-add
                 const float k = fmaf(fp, ks[r], kb[r]) - kc;
-                const float wk = __builtin_amdgcn_fractf(k);
+                wk[r] = __builtin_amdgcn_fractf(k);
                 const lds_float *row = lds_ptr(__umul24((uint32_t)k, 4u * kQS) + colb);
-                const float v00 = row[0], v10 = row[1];
-                const float v01 = row[kQS], v11 = row[kQS + 1];
-                const float lo = fmaf(wq, v10 - v00, v00);
-                const float hi = fmaf(wq, v11 - v01, v01);
-                acc[r] += fmaf(wk, hi - lo, lo);
+                v00[r] = row[0];
+                v10[r] = row[1];
+                v01[r] = row[kQS];
+                v11[r] = row[kQS + 1];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r) {
+            if (r < R) {
+                const float lo = fmaf(wq, v10[r] - v00[r], v00[r]);
+                const float hi = fmaf(wq, v11[r] - v01[r], v01[r]);
+                acc[r] += fmaf(wk[r], hi - lo, lo);
             }
         }
     }
