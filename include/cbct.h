@@ -161,8 +161,10 @@ cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
 cbct_status cbct_batch_forward(int n, const cbct_geom *const *g, const void *const *vols,
                                void *const *sinos, cbct_dtype vt, cbct_dtype st, void *stream);
 
-/* Batched adjoint, the counterpart of cbct_batch_forward (it uses the same
- * library-owned buffer as cbct_adjoint, sized for all cases together). */
+/* Batched adjoint, the counterpart of cbct_batch_forward: one launch per 16
+ * cases whose geometry takes the bricked kernel (the others on their own).
+ * It uses the same library-owned buffer as cbct_adjoint, sized for the
+ * cases of one launch together. */
 cbct_status cbct_batch_adjoint(int n, const cbct_geom *const *g, const void *const *sinos,
                                void *const *vols, cbct_dtype st, cbct_dtype vt, void *stream);
 

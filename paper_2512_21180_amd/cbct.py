@@ -275,7 +275,8 @@ def batch_forward(geoms, vols, outs=None, out_dtype=None):
 
 
 def batch_adjoint(geoms, sinos, outs=None, out_dtype=None):
-    """One launch: vols[i] = A_i^T sinos[i] for heterogeneous single-channel cases."""
+    """vols[i] = A_i^T sinos[i] for heterogeneous single-channel cases, in one
+    launch per 16 cases."""
     n = len(geoms)
     assert len(sinos) == n and n > 0
     for g, s in zip(geoms, sinos):
