@@ -49,6 +49,7 @@
 #include <algorithm>
 
 #include "cbct_internal.h"
+#include "cbct_lds.h"
 #include "cbct_storage.h"
 
 namespace cbct {
@@ -67,14 +68,8 @@ struct BrickArgs {
 
 __device__ inline float sat(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
-// LDS addresses as plain 32-bit numbers: a run's address comes out of one
-// float-to-integer conversion with no base to add.
-typedef __attribute__((address_space(3))) const float lds_float;
-__device__ inline uint32_t lds_addr(const float *p)
-{
-    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const float *)p;
-}
-__device__ inline lds_float *lds_ptr(uint32_t a) { return (lds_float *)(uintptr_t)a; }
+// A run's LDS address is a plain 32-bit number (lds_addr, lds_ptr): it comes
+// out of one float-to-integer conversion with no base to add.
 
 // Fractional panel column of the ray through (x, y, .) and its source-panel
 // scale lambda (a point at height z lands at V = lambda z).  Used only for a

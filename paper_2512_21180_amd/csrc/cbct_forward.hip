@@ -24,6 +24,7 @@
 #include <algorithm>
 
 #include "cbct_internal.h"
+#include "cbct_lds.h"
 #include "cbct_storage.h"
 
 namespace cbct {
@@ -32,13 +33,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kMaxR = 8;       // rays per thread
 
-// LDS addresses as 32-bit numbers (a row address is one multiply-add).
-typedef __attribute__((address_space(3))) const float lds_float;
-__device__ inline uint32_t lds_addr(const float *p)
-{
-    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const float *)p;
-}
-__device__ inline lds_float *lds_ptr(uint32_t a) { return (lds_float *)(uintptr_t)a; }
 constexpr int kQS = 65;        // LDS row stride (floats): box rows are <= 64 wide
 constexpr int kMaxRows = 32;   // box rows (z) per plane
 constexpr int kSlots = kMaxRows / 4;
@@ -196,22 +190,23 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
         const float q = fmaf(fp, c.ps, c.pb);
         const float qf = floorf(q);
         const float wq = q - qf;
-        // byte address of this column's position in box row 0
-        const uint32_t colb = lds_addr(buf) + 4u * (uint32_t)((int)qf - cb.qlo);
-        const float kc = (float)cb.klo;
+        // byte address this column would have in z row 0 (the box's first
+        // row, klo, lies at its position in box row 0)
+        const int colz =
+            (int)(lds_addr(buf) + 4u * (uint32_t)((int)qf - cb.qlo)) - cb.klo * (4 * kQS);
         // all rays' reads first, then their arithmetic: the reads of the
         // rays overlap instead of each ray waiting for its own
         float wk[kMaxR], v00[kMaxR], v10[kMaxR], v01[kMaxR], v11[kMaxR];
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             if (r < R) {
-                // k >= 0 inside the box (its lowest row lies below every
-                // ray), so truncation is the floor and the fraction exact:
-                // the same values as floor and subtraction, two operations
-                // fewer with the row address in one multiply-add
-                const float k = fmaf(fp, ks[r], kb[r]) - kc;
+                // z index k of the ray on this plane: its weight is the
+                // exact fraction of k, its row address one floor conversion
+                // and one multiply-add (every ray's floor(k) lies in the box
+                // rows [klo, klo + kw - 1), so the address is inside the box)
+                const float k = fmaf(fp, ks[r], kb[r]);
                 wk[r] = __builtin_amdgcn_fractf(k);
-                const lds_float *row = lds_ptr(__umul24((uint32_t)k, 4u * kQS) + colb);
+                const lds_float *row = lds_ptr((uint32_t)mad_i24(floor_i32(k), 4 * kQS, colz));
                 v00[r] = row[0];
                 v10[r] = row[1];
                 v01[r] = row[kQS];

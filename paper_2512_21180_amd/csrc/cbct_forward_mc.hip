@@ -31,6 +31,7 @@
 #include <algorithm>
 
 #include "cbct_internal.h"
+#include "cbct_lds.h"
 #include "cbct_storage.h"
 
 namespace cbct {
@@ -41,13 +42,6 @@ constexpr int kMaxR = 8;        // rays per thread
 constexpr int kBoxChunk = 256;  // planes whose boxes are tabulated at a time
 static_assert(kBoxChunk == kThreads, "the box table is filled one plane per thread");
 
-// LDS addresses as 32-bit numbers (a row address is one multiply-add).
-typedef __attribute__((address_space(3))) const float lds_float;
-__device__ inline uint32_t lds_addr(const float *p)
-{
-    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const float *)p;
-}
-__device__ inline lds_float *lds_ptr(uint32_t a) { return (lds_float *)(uintptr_t)a; }
 
 template <int N> struct VecOf;
 template <> struct VecOf<2> { using T = float2; };
@@ -221,19 +215,21 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
         const float q = fmaf(fp, c.ps, c.pb);
         const float qf = floorf(q);
         const float wq = q - qf;
-        // byte address of this column's position in box row 0
-        const uint32_t colb = lds_addr(buf) + (uint32_t)sizeof(V0) * (uint32_t)((int)qf - cb.qlo);
-        const float kc = (float)cb.klo;
+        // byte address this column would have in z row 0 (as in the
+        // single-channel sweep)
+        const int colz = (int)(lds_addr(buf) + (uint32_t)sizeof(V0) * (uint32_t)((int)qf - cb.qlo)) -
+                         cb.klo * (int)(sizeof(V0) * QS);
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             if (r < R) {
-                // as in the single-channel sweep: k >= 0 in the box, so the
-                // truncation is the floor and the fraction exact
-                const float k = fmaf(fp, ks[r], kb[r]) - kc;
+                // as in the single-channel sweep: the exact fraction of the
+                // ray's z index and its row address from one floor conversion
+                const float k = fmaf(fp, ks[r], kb[r]);
                 const float wk = __builtin_amdgcn_fractf(k);
                 // (a generic pointer made from the LDS address: the
                 // compiler still reads it from LDS)
-                const V0 *row = (const V0 *)(lds_ptr(__umul24((uint32_t)k, (uint32_t)sizeof(V0) * QS) + colb));
+                const V0 *row = (const V0 *)(lds_ptr(
+                    (uint32_t)mad_i24(floor_i32(k), (int)(sizeof(V0) * QS), colz)));
                 const V0 a00 = row[0], a10 = row[1];
                 const V0 a01 = row[QS], a11 = row[QS + 1];
 #pragma unroll
