@@ -56,6 +56,10 @@ namespace cbct {
 namespace {
 
 constexpr int kThreads = 256;
+// Fourth word of a buffer resource on the gfx9 family (gfx950 included):
+// 32-bit data format, no swizzle; raw dword loads use only the base, the
+// size (for the range check) and this word's defaults.
+constexpr int kBufferWord3 = 0x00020000;
 
 struct BrickArgs {
     DevGeom g;
@@ -241,7 +245,7 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const fl
                                              typename VS::T *vol, float *lds)
 {
     constexpr int kBK = 4 * KV;
-    constexpr int kSB = 8;   // rows per staging batch (loads in flight)
+    constexpr int kSB = 24;  // rows per staging batch (loads in flight)
     const DevGeom &g = A.g;
     const int HS = A.HS;
     float *yt = lds;                                    // ds-weighted panel window
@@ -309,35 +313,50 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const fl
         __syncthreads();   // previous angle's readers are done
         // Columns on lanes, rows on waves (stride 4).  The loads of kSB rows
         // are issued before any of them is used, so their latencies overlap
-        // instead of adding up row after row.
-        const float *proj = ws + (size_t)a * g.nv * g.nu;   // this projection, ds-weighted
+        // instead of adding up row after row.  They go through a buffer
+        // resource holding exactly rows V0 .. V1 of this projection: the
+        // range check returns zero for every row past V1 (the window's zero
+        // rows and a batch's rows past Hs) without touching memory, so no
+        // load needs a test of its own.  Byte offsets within the rows are
+        // 32-bit (nv nu < 2^24).
+        const float *proj = ws + ((size_t)a * g.nv + V0) * g.nu;   // row V0, ds-weighted
+        const __amdgpu_buffer_rsrc_t rows =
+            __builtin_amdgcn_make_buffer_rsrc((void *)proj, (short)0, (V1 - V0 + 1) * g.nu * 4,
+                                              kBufferWord3);
+        const int row_bytes = 4 * g.nu;
         for (int uu = lane; uu < Wc; uu += 64) {
-            if (w == 0) {   // uniform: one wave writes the column table
+            // one wave also writes the column table (uniform branches); its
+            // load is issued with the rows' and stored after them, so that
+            // wave does not wait for it before issuing its row loads
+            float4 ctab;
+            if (w == 0) {
                 const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
-                cr[uu] = make_float4(col.pb, col.ps, col.t0, col.tau);
+                ctab = make_float4(col.pb, col.ps, col.t0, col.tau);
             }
-            const int u = U0 + uu;
+            const int cb = 4 * (U0 + uu);   // byte offset of the column in a row
             float *dst = yt + (size_t)uu * HS;
             for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
-                // rows past V1 (stored as zeros) load row V1 instead, so no
-                // load sits behind a branch that would make it wait for its
-                // value; 32-bit offsets within the projection (nv nu < 2^24)
+                // the batch's first row for this lane, kept in one register
+                // (the empty asm stops the compiler from hoisting kSB lane
+                // offsets out of the loop, which costs kSB registers); each
+                // load adds a wave-uniform row offset
+                int off = cb + vv0 * row_bytes;
+                asm volatile("" : "+v"(off));
                 float val[kSB];
-                bool live[kSB];
 #pragma unroll
-                for (int jj = 0; jj < kSB; ++jj) {
-                    const int v = V0 + vv0 + 4 * jj;
-                    live[jj] = v <= V1;
-                    const int vr = min(v, V1);
-                    val[jj] = proj[(uint32_t)(__mul24(vr, g.nu) + u)];
-                }
+                for (int jj = 0; jj < kSB; ++jj)
+                    val[jj] = __builtin_bit_cast(
+                        float, __builtin_amdgcn_raw_buffer_load_b32(
+                                   rows, off + 4 * jj * row_bytes, 0, 0));
+                // rows past Hs (zeros) all go to row HS - 1, a spare row no
+                // tap reads (HS > H >= Hs): with every store unconditional no
+                // load can be moved behind the wait for the others
 #pragma unroll
-                for (int jj = 0; jj < kSB; ++jj) {
-                    const int vv = vv0 + 4 * jj;
-                    if (vv < Hs)
-                        dst[vv] = live[jj] ? val[jj] : 0.0f;
-                }
+                for (int jj = 0; jj < kSB; ++jj)
+                    dst[min(vv0 + 4 * jj, HS - 1)] = val[jj];
             }
+            if (w == 0)
+                cr[uu] = ctab;
         }
         __syncthreads();
 

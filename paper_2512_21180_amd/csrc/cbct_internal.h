@@ -121,7 +121,7 @@ static_assert(sizeof(BrickWin) == 16, "BrickWin layout");
 struct AdjPlan {
     bool ok = false;   // false: fall back to the one-thread-per-voxel kernel
     int W = 0, H = 0;  // footprint bounds (columns, rows)
-    int WS = 0;        // LDS column stride of the window (floats, 2 mod 4)
+    int WS = 0;        // LDS column stride of the window (floats, 2 mod 4, > H)
     int NTmax = 0;     // largest row-tap count
     int KV = 4;        // voxels per thread along z: bricks are kAdjBI x kAdjBJ x 4 KV
     const BrickWin *wins = nullptr;   // device: [n_angles][nby][nbx]

@@ -285,7 +285,7 @@ def _adj_brick_check(h, bx, by, bz, angles, bk):
         assert V1 == V1u
         Hs = max(V1 - V0 + 1, NT)
         VS1 = max(V1 - NT + 1, V0)
-        assert U1 - U0 + 1 <= W_ and Hs <= H_ and H_ <= WS and WS % 4 == 2
+        assert U1 - U0 + 1 <= W_ and Hs <= H_ and H_ < WS and WS % 4 == 2
         # lane roles: on x planes, plane i and in-plane segment [s, s + 1) of y
         # for s = j0 - 1 .. j0 + BJ - 1; on y planes, plane j and segment of x
         # for s = i0 - 1 .. i0 + BI - 1
