@@ -122,7 +122,8 @@ cbct_status cbct_geom_sizes(const cbct_geom *g, uint64_t *n_vox, uint64_t *n_sin
  * sino = A vol for n_channels >= 1 stacked channels.  vol (storage vt) is
  * [C][nz][ny][nx]; sino (storage st) is [C][n_angles][nv][nu].  Geometries
  * whose ray tiles spread over more voxels than the tiled kernel stages, or
- * whose volume channel takes 4 GiB or more in FP32, run a one-thread-per-ray
+ * whose volume channel with 64 more z planes reaches 4 GiB in FP32, run a
+ * one-thread-per-ray
  * kernel with the same arithmetic (slower; cbct_geom_plan_info tells which).
  */
 cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,

@@ -56,10 +56,6 @@ namespace cbct {
 namespace {
 
 constexpr int kThreads = 256;
-// Fourth word of a buffer resource on the gfx9 family (gfx950 included):
-// 32-bit data format, no swizzle; raw dword loads use only the base, the
-// size (for the range check) and this word's defaults.
-constexpr int kBufferWord3 = 0x00020000;
 
 struct BrickArgs {
     DevGeom g;

@@ -127,34 +127,30 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     // plane stay in flight while this plane is summed
     using Raw = typename VS::Raw;
     // Slot s of wave w holds box row w + 4 s, z index k0 + 4 s with
-    // k0 = klo + w: live for s in [s_lo, s_hi) (inside the box rows and the
-    // volume, uniform per wave) and in-plane index inside the volume (per
-    // lane).  Offsets are 32-bit byte offsets from the volume base (the plan
-    // keeps tiled volumes under 4 GiB), advanced by 4 sk per slot.
+    // k0 = klo + w; the wave loads the slots inside the box rows (a uniform
+    // count).  Loads go through a buffer resource over the volume, whose
+    // range check returns zero for everything outside it: slots below z
+    // index 0 (their 32-bit offsets wrap past the end; the plan keeps the
+    // volume with 64 more planes under 4 GiB), slots past the top, and lanes
+    // outside the volume in plane (their first offset is set to the end).
+    const uint32_t vbytes = (uint32_t)sk * (uint32_t)g.nz * (uint32_t)sizeof(typename VS::T);
+    const __amdgpu_buffer_rsrc_t vres =
+        __builtin_amdgcn_make_buffer_rsrc((void *)v, (short)0, (int)vbytes, kBufferWord3);
     const uint32_t step = 4u * (uint32_t)sk * (uint32_t)sizeof(typename VS::T);
-    // The live slots form a wave-uniform bit mask (one scalar bit test per
-    // slot) and the lane test is one exec region for all slots: per-slot
-    // range tests and exec juggling had made the sweep issue nearly as many
-    // scalar as vector instructions.
     auto fetch = [&](int p, const Box &b, Raw (&st)[kSlots]) {
         const int q = b.qlo + lane;
         const bool qin = lane < b.qw && (unsigned)q < (unsigned)nq;
-        const int k0 = b.klo + w;
-        const int s_lo = k0 >= 0 ? 0 : (3 - k0) >> 2;
-        const int s_hi = min((b.kw - w + 3) >> 2, (g.nz - k0 + 3) >> 2);
-        const uint32_t live = s_hi > s_lo ? ((1u << s_hi) - 1u) & ~((1u << s_lo) - 1u) : 0u;
-        // modular: exact whenever the slot is live
+        const int n_sl = (b.kw - w + 3) >> 2;
+        // modular: exact for slots inside the volume
         const uint32_t off0 =
-            (uint32_t)(q * sq + p * sp + k0 * sk) * (uint32_t)sizeof(typename VS::T);
+            qin ? (__umul24((uint32_t)q, (uint32_t)sq) + (uint32_t)p * (uint32_t)sp +
+                   (uint32_t)(b.klo + w) * (uint32_t)sk) *
+                      (uint32_t)sizeof(typename VS::T)
+                : vbytes;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s)
-            st[s] = Raw(0);
-        if (qin) {
-#pragma unroll
-            for (int s = 0; s < kSlots; ++s)
-                if (live & (1u << s))
-                    st[s] = VS::raw_at(v, off0 + (uint32_t)s * step);
-        }
+            if (s < n_sl)
+                st[s] = VS::buf_at(vres, off0 + (uint32_t)s * step);
     };
 
     __syncthreads();   // the previous work item's readers of lds are done
@@ -224,15 +220,28 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     }
 
     if (uc < T.nu_t) {
-        const float ds0 = c.dsf;
+        // every ray's length factor first, its row record loaded with the
+        // others' (the empty asm keeps the compiler from moving each load
+        // behind its ray's store test, where the loads would wait one by one)
+        // (the row index passes through an empty asm here, so that the
+        // loads are not hoisted above the sweep, where they would hold
+        // eight registers throughout)
+        int rb = row0;
+        asm volatile("" : "+v"(rb));
+        float ds[kMaxR];
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r)
+            ds[r] = g.rows[T.v0 + min(rb + r, T.nv_t - 1)].y;
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r) {
+            ds[r] = ray_ds(c.dsf, c.n2, ds[r]);
+            asm volatile("" : "+v"(ds[r]));
+        }
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             const int vr = row0 + r;
-            if (r < R && vr < T.nv_t) {
-                const int iv = T.v0 + vr;
-                const float ds = ray_ds(ds0, c.n2, g.rows[iv].y);
-                SS::st(sino, ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + uc, acc[r] * ds);
-            }
+            if (r < R && vr < T.nv_t)
+                SS::st(sino, ((size_t)T.a * g.nv + T.v0 + vr) * g.nu + T.u0 + uc, acc[r] * ds[r]);
         }
     }
 }

@@ -47,6 +47,17 @@ template <int N> struct VecOf;
 template <> struct VecOf<2> { using T = float2; };
 template <> struct VecOf<4> { using T = float4; };
 
+// One packed voxel through a buffer resource (zero outside its range).
+template <class V> __device__ __forceinline__ V buf_vec(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ float2 buf_vec<float2>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float4 buf_vec<float4>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 __device__ __forceinline__ float comp(float2 v, int i) { return i == 0 ? v.x : v.y; }
 __device__ __forceinline__ float comp(float4 v, int i)
 {
@@ -150,33 +161,28 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
         return b;
     };
     // Slot s of wave w holds box row w + 4 s: one vector load per slot from
-    // the packed volume, at a 32-bit byte offset (16 bytes per voxel stay
-    // under 4 GiB where this kernel runs).
-    const uint32_t step = 4u * (uint32_t)sk;
-    const V0 *vg = (const V0 *)M.vg;
+    // the packed volume through a buffer resource (zero outside it, as in
+    // the single-channel sweep: slots below or above the volume, and lanes
+    // outside it in plane, whose first offset is set to the end; 32-bit
+    // offsets, the volume with 64 more planes stays under 4 GiB where this
+    // kernel runs).
+    const uint32_t vbytes = (uint32_t)sk * (uint32_t)g.nz * (uint32_t)sizeof(V0);
+    const __amdgpu_buffer_rsrc_t vres =
+        __builtin_amdgcn_make_buffer_rsrc((void *)M.vg, (short)0, (int)vbytes, kBufferWord3);
+    const uint32_t step = 4u * (uint32_t)sk * (uint32_t)sizeof(V0);
     auto fetch = [&](int p, const Box &b, V0 (&st0)[kSlots]) {
         const int q = b.qlo + lane;
         const bool qin = lane < b.qw && (unsigned)q < (unsigned)nq;
-        const int k0 = b.klo + w;
-        const int s_lo = k0 >= 0 ? 0 : (3 - k0) >> 2;
-        const int s_hi = min((b.kw - w + 3) >> 2, (g.nz - k0 + 3) >> 2);
-        // live slots as a wave-uniform bit mask, the lane test as one exec
-        // region (as in the single-channel sweep)
-        const uint32_t live = s_hi > s_lo ? ((1u << s_hi) - 1u) & ~((1u << s_lo) - 1u) : 0u;
-        // modular: exact whenever the slot is live; byte offsets from the
-        // (scalar) bases, so the loads take the base in scalar registers
-        const uint32_t off0 = (uint32_t)(q * sq + p * sp + k0 * sk);
+        const int n_sl = (b.kw - w + 3) >> 2;
+        const uint32_t off0 =
+            qin ? (__umul24((uint32_t)q, (uint32_t)sq) + (uint32_t)p * (uint32_t)sp +
+                   (uint32_t)(b.klo + w) * (uint32_t)sk) *
+                      (uint32_t)sizeof(V0)
+                : vbytes;
 #pragma unroll
         for (int s = 0; s < kSlots; ++s)
-            st0[s] = V0{};
-        if (qin) {
-#pragma unroll
-            for (int s = 0; s < kSlots; ++s)
-                if (live & (1u << s)) {
-                    const uint32_t at = off0 + (uint32_t)s * step;
-                    st0[s] = *(const V0 *)((const char *)vg + at * (uint32_t)sizeof(V0));
-                }
-        }
+            if (s < n_sl)
+                st0[s] = buf_vec<V0>(vres, off0 + (uint32_t)s * step);
     };
 
     __syncthreads();   // the previous work item's readers of lds are done
@@ -245,17 +251,30 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
     }
 
     if (uc < T.nu_t) {
-        const float ds0 = c.dsf;
+        // length factors first, the row records loaded together (as in the
+        // single-channel sweep)
+        // (the row index passes through an empty asm here, so that the
+        // loads are not hoisted above the sweep, where they would hold
+        // eight registers throughout)
+        int rb = row0;
+        asm volatile("" : "+v"(rb));
+        float ds[kMaxR];
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r)
+            ds[r] = g.rows[T.v0 + min(rb + r, T.nv_t - 1)].y;
+#pragma unroll
+        for (int r = 0; r < kMaxR; ++r) {
+            ds[r] = ray_ds(c.dsf, c.n2, ds[r]);
+            asm volatile("" : "+v"(ds[r]));
+        }
 #pragma unroll
         for (int r = 0; r < kMaxR; ++r) {
             const int vr = row0 + r;
             if (r < R && vr < T.nv_t) {
-                const int iv = T.v0 + vr;
-                const float ds = ray_ds(ds0, c.n2, g.rows[iv].y);
-                const size_t at = ((size_t)T.a * g.nv + iv) * g.nu + T.u0 + uc;
+                const size_t at = ((size_t)T.a * g.nv + T.v0 + vr) * g.nu + T.u0 + uc;
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch)
-                    M.sino[ch][at] = acc[ch][r] * ds;
+                    M.sino[ch][at] = acc[ch][r] * ds[r];
             }
         }
     }
@@ -368,8 +387,8 @@ hipError_t launch_mc_groups(McArgs &B, const cbct_geom *const *gs, float *const 
 int forward_mc_max_channels(const cbct_geom *g)
 {
     const FwdPlan &p = g->fwd;
-    const uint64_t nvox = (uint64_t)g->desc.nx * g->desc.ny * g->desc.nz;
-    if (!p.ok || p.BQ > 64 || p.BK > 32 || nvox * 16 >= (1ull << 32))
+    const uint64_t nvox64 = (uint64_t)g->desc.nx * g->desc.ny * (g->desc.nz + 64);
+    if (!p.ok || p.BQ > 64 || p.BK > 32 || nvox64 * 16 >= (1ull << 32))
         return 0;
     return small_layout(p) ? 4 : 2;
 }

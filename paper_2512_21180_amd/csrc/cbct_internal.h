@@ -227,7 +227,7 @@ hipError_t launch_adjoint_batch(int n, const cbct_geom *const *g, const void *co
 // channel's output is bitwise equal to the single-channel tiled kernel's.
 // The largest C a geometry allows: 4 where its boxes fit 39 x 19 voxels
 // (staged in 41 x 20 LDS rows), else 2 (65 x 32), 0 where the plan is not
-// tiled or 16 bytes per voxel reach 4 GiB.
+// tiled or 16 bytes per voxel reach 4 GiB with 64 more z planes.
 constexpr int kMaxMcChannels = 4;
 constexpr int kMaxMcGroups = 8;
 int forward_mc_max_channels(const cbct_geom *g);

@@ -1,6 +1,7 @@
 // Small device helpers shared by the projector kernels: LDS addresses as
 // 32-bit numbers (so a row address is one integer multiply-add), a
-// one-instruction floor-to-integer conversion and a 24-bit multiply-add.
+// one-instruction floor-to-integer conversion, a 24-bit multiply-add and the
+// buffer-resource word the staging loads use.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,5 +37,10 @@ __device__ inline int mad_i24(int a, int b, int c)
     asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
     return r;
 }
+
+// Fourth word of a buffer resource on the gfx9 family (gfx950 included):
+// 32-bit data format, no swizzle; raw loads use only the base, the size (for
+// the range check: offsets at or past it read zero) and this word.
+constexpr int kBufferWord3 = 0x00020000;
 
 }  // namespace cbct

@@ -9,8 +9,9 @@
 // or the last plane), widened by the rounding margins the kernel relies on.
 // TU is 64 columns, or 32 where 64 columns of rays spread wider than 64
 // voxels (pixels coarser than the voxels); TV is the largest of 256 / TU
-// times 8, 4, 2, 1 rows whose boxes fit.  Volumes of 4 GiB or more (the
-// kernel's offsets are 32-bit) take the one-thread-per-ray kernel.
+// times 8, 4, 2, 1 rows whose boxes fit.  Volumes that reach 4 GiB with 64
+// more z planes (the kernel's offsets are 32-bit, and offsets below the
+// volume must wrap past its end) take the one-thread-per-ray kernel.
 //
 // Adjoint: the volume is cut into 8 x 7 x 4 KV bricks (KV = 4, 2 or 1 voxels
 // per thread along z).  For every angle a brick's support (voxel centres +-
@@ -250,8 +251,10 @@ void plan_host(cbct_geom *g)
     g->tiles.clear();
     TileBuild tb;
     int R = 0, TU = 64;
-    // the tiled kernel addresses one volume channel with 32-bit byte offsets
-    const bool off32 = (uint64_t)d.nx * d.ny * d.nz * sizeof(float) < (1ull << 32);
+    // the tiled kernel addresses one volume channel with 32-bit byte offsets,
+    // those of slots below the volume wrapping past its end (64 planes of
+    // margin)
+    const bool off32 = (uint64_t)d.nx * d.ny * (d.nz + 64) * sizeof(float) < (1ull << 32);
     for (int tu : {64, 32}) {
         if (!off32)
             break;

@@ -18,6 +18,8 @@ CASES = {
     "crop_c2": W.cropped(W.C2, n_angles=24, nu=160, nv=96, n=64),   # 41 x 20 layout
     "ragged": RAGGED,                                                 # 41 x 20, odd sizes
     "c1": W.C1,                                                       # 65 x 32 layout
+    # boxes past both ends of a 6-plane slab
+    "thin_slab": W.geometry(10, 60, 90, 1.0, 1.0, 30, 26, 6, 1.5, off_u=4.0, off_v=3.0),
 }
 
 

@@ -77,7 +77,11 @@ LONG_SWEEP = W.geometry(6, 48, 24, 1.6, 1.6, 300, 40, 20, 1.0, off_u=5.0)
 # a 40000-column panel whose volume projects near column 35000: the
 # adjoint's window columns (packed 16 + 16 bits) lie above 32767
 WIDE_PANEL = W.geometry(3, 40000, 16, 0.01, 0.01, 16, 16, 8, 0.05, off_u=-150.0)
+# a 9 mm slab under a 90 mm panel: most rays pass above or below the volume,
+# so the forward's staged boxes reach past both its ends (read as zeros)
+THIN_SLAB = W.geometry(10, 60, 90, 1.0, 1.0, 30, 26, 6, 1.5, off_u=4.0, off_v=3.0)
 CASES = {
+    "thin_slab": THIN_SLAB,
     "fallback_fwd": FINE_VOX,
     "fallback_adj": COARSE_VOX,
     "ragged": RAGGED,

@@ -440,10 +440,11 @@ def test_brick_depth_follows_the_window():
 
 
 def test_tiled_forward_needs_32bit_offsets():
-    """The tiled forward addresses a volume channel with 32-bit byte offsets:
-    volumes of 4 GiB or more (FP32) take the one-thread-per-ray kernel."""
-    small = W.geometry(4, 64, 16, 0.1, 0.1, 1024, 1024, 1023, 0.2)
-    big = W.geometry(4, 64, 16, 0.1, 0.1, 1024, 1024, 1024, 0.2)
+    """The tiled forward addresses a volume channel with 32-bit byte offsets,
+    those below the volume wrapping past its end: volumes that reach 4 GiB
+    (FP32) with 64 more z planes take the one-thread-per-ray kernel."""
+    small = W.geometry(4, 64, 16, 0.1, 0.1, 1024, 1024, 1024 - 64 - 1, 0.2)
+    big = W.geometry(4, 64, 16, 0.1, 0.1, 1024, 1024, 1024 - 64, 0.2)
     hs, hb = Host(small), Host(big)
     try:
         assert hs.info[0] == 1
