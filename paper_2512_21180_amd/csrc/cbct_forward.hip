@@ -128,9 +128,9 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     using Raw = typename VS::Raw;
     // Slot s of wave w holds box row w + 4 s, z index k0 + 4 s with
     // k0 = klo + w; the wave loads the slots inside the box rows (a uniform
-    // count).  Loads go through a buffer resource over the volume, whose
-    // range check returns zero for everything outside it: slots below z
-    // index 0 (their 32-bit offsets wrap past the end; the plan keeps the
+    // count).  FP32 loads go through a buffer resource over the volume,
+    // whose range check returns zero for everything outside it: slots below
+    // z index 0 (their 32-bit offsets wrap past the end; the plan keeps the
     // volume with 64 more planes under 4 GiB), slots past the top, and lanes
     // outside the volume in plane (their first offset is set to the end).
     const uint32_t vbytes = (uint32_t)sk * (uint32_t)g.nz * (uint32_t)sizeof(typename VS::T);
@@ -140,17 +140,39 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     auto fetch = [&](int p, const Box &b, Raw (&st)[kSlots]) {
         const int q = b.qlo + lane;
         const bool qin = lane < b.qw && (unsigned)q < (unsigned)nq;
-        const int n_sl = (b.kw - w + 3) >> 2;
-        // modular: exact for slots inside the volume
-        const uint32_t off0 =
-            qin ? (__umul24((uint32_t)q, (uint32_t)sq) + (uint32_t)p * (uint32_t)sp +
-                   (uint32_t)(b.klo + w) * (uint32_t)sk) *
-                      (uint32_t)sizeof(typename VS::T)
-                : vbytes;
+        if constexpr (sizeof(typename VS::T) == 4) {
+            const int n_sl = (b.kw - w + 3) >> 2;
+            // modular: exact for slots inside the volume
+            const uint32_t off0 =
+                qin ? (__umul24((uint32_t)q, (uint32_t)sq) + (uint32_t)p * (uint32_t)sp +
+                       (uint32_t)(b.klo + w) * (uint32_t)sk) *
+                          (uint32_t)sizeof(typename VS::T)
+                    : vbytes;
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s)
-            if (s < n_sl)
-                st[s] = VS::buf_at(vres, off0 + (uint32_t)s * step);
+            for (int s = 0; s < kSlots; ++s)
+                if (s < n_sl)
+                    st[s] = VS::buf_at(vres, off0 + (uint32_t)s * step);
+        } else {
+            // 16-bit volumes: masked global loads (slots inside the box rows
+            // and the volume as a wave-uniform bit mask, the lane test one
+            // exec region): 16-bit buffer loads staged them more slowly
+            const int k0 = b.klo + w;
+            const int s_lo = k0 >= 0 ? 0 : (3 - k0) >> 2;
+            const int s_hi = min((b.kw - w + 3) >> 2, (g.nz - k0 + 3) >> 2);
+            const uint32_t live =
+                s_hi > s_lo ? ((1u << s_hi) - 1u) & ~((1u << s_lo) - 1u) : 0u;
+            const uint32_t off0 =
+                (uint32_t)(q * sq + p * sp + k0 * sk) * (uint32_t)sizeof(typename VS::T);
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s)
+                st[s] = Raw(0);
+            if (qin) {
+#pragma unroll
+                for (int s = 0; s < kSlots; ++s)
+                    if (live & (1u << s))
+                        st[s] = VS::raw_at(v, off0 + (uint32_t)s * step);
+            }
+        }
     };
 
     __syncthreads();   // the previous work item's readers of lds are done

@@ -1,8 +1,8 @@
 // Storage conversions for the projector kernels: FP32 arithmetic on FP32,
 // BF16 or FP16 buffers (widened on load, rounded to nearest-even on store).
 // `raw` loads the stored bits into a 32-bit register (`raw_at`: at a 32-bit
-// byte offset from the base; `buf_at`: through a buffer resource, zero
-// outside its range) and `wide` widens them:
+// byte offset from the base; `buf_at`, FP32 only: through a buffer
+// resource, zero outside its range) and `wide` widens them:
 // a kernel that keeps loads in flight across other work holds raw values and
 // widens them where they are used (widening, or packing two 16-bit values
 // into one register, right after the load would wait for it).
@@ -40,10 +40,6 @@ struct BF16 {
     {
         return *(const T *)((const char *)p + byte_off);
     }
-    __device__ static Raw buf_at(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
-    {
-        return __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0);
-    }
     __device__ static float wide(Raw x) { return __uint_as_float(x << 16); }
     __device__ static void st(T *p, size_t i, float v)
     {
@@ -68,10 +64,6 @@ struct F16 {
     __device__ static Raw raw_at(const T *p, uint32_t byte_off)
     {
         return __builtin_bit_cast(uint16_t, *(const T *)((const char *)p + byte_off));
-    }
-    __device__ static Raw buf_at(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
-    {
-        return __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0);
     }
     __device__ static float wide(Raw x)
     {
