@@ -331,8 +331,14 @@ forward_batch(BatchFwdArgs B)
     const TileRec T = C.tiles[item - B.first[cs]];
     if (T.nu_t == 0)
         return;
-    sweep_tile<VS, SS>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
-                       (typename SS::T *)C.sino, lds);
+    // cases with the usual rays per thread take the sweep specialised for it
+    // (a uniform branch; the bits do not depend on the variant)
+    if (C.R == kMaxR)
+        sweep_tile<VS, SS, kMaxR>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
+                                  (typename SS::T *)C.sino, lds);
+    else
+        sweep_tile<VS, SS>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
+                           (typename SS::T *)C.sino, lds);
 }
 
 }  // namespace
