@@ -125,6 +125,12 @@ cbct_status cbct_geom_sizes(const cbct_geom *g, uint64_t *n_vox, uint64_t *n_sin
  * whose volume channel with 64 more z planes reaches 4 GiB in FP32, run a
  * one-thread-per-ray
  * kernel with the same arithmetic (slower; cbct_geom_plan_info tells which).
+ * The tiled kernel first writes the volume with x and y swapped (C x
+ * nx*ny*nz elements of storage vt) into the device buffer the library owns
+ * (the one cbct_adjoint uses: the first call on a device, or a larger one,
+ * allocates; calls on different streams are ordered on it): tiles that
+ * sweep x planes stage their boxes from it.  Multichannel FP32 stacks pack
+ * their channels there instead.
  */
 cbct_status cbct_forward(const cbct_geom *g, const void *vol, cbct_dtype vt,
                          void *sino, cbct_dtype st, int n_channels, void *stream);

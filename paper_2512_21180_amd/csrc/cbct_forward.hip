@@ -53,9 +53,15 @@ constexpr size_t kFwdLds = 2 * (size_t)kMaxRows * kQS * sizeof(float) + kBoxChun
 // plans' usual 8 rays per thread): the per-ray tests then vanish, which
 // matters because the sweep issues nearly as many scalar as vector
 // instructions and a SIMD takes one of each per four cycles.
+// vt: the volume with x and y swapped ([nz][nx][ny]) or null.  Tiles that
+// sweep x planes read their boxes from it, so a box row (fixed z, in-plane
+// index y) is contiguous; in the volume itself its voxels lie nx apart, a
+// cache line each (the clinical forward: 12.2 ms reading them strided,
+// 8.8 ms from the transposed copy).
 template <class VS, class SS, int RC = 0>
 __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, int R_rt, int tub,
                            const typename VS::T *__restrict__ v,
+                           const typename VS::T *__restrict__ vt,
                            typename SS::T *__restrict__ sino, float *lds)
 {
     const int R = RC > 0 ? RC : R_rt;
@@ -89,8 +95,10 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
 
     const bool xp = T.cls == 0;
     const int nq = xp ? g.ny : g.nx;
-    const int sp = xp ? 1 : g.nx;      // plane stride
-    const int sq = xp ? g.nx : 1;      // in-plane stride
+    const bool tr = xp && vt != nullptr;   // x planes from the transposed copy
+    const typename VS::T *src = tr ? vt : v;
+    const int sp = xp ? (tr ? g.ny : 1) : g.nx;   // plane stride
+    const int sq = xp && !tr ? g.nx : 1;         // in-plane stride
     const int sk = g.nx * g.ny;        // z stride (volumes have < 2^31 voxels)
 
     struct Box {
@@ -135,7 +143,7 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
     // outside the volume in plane (their first offset is set to the end).
     const uint32_t vbytes = (uint32_t)sk * (uint32_t)g.nz * (uint32_t)sizeof(typename VS::T);
     const __amdgpu_buffer_rsrc_t vres =
-        __builtin_amdgcn_make_buffer_rsrc((void *)v, (short)0, (int)vbytes, kBufferWord3);
+        __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)vbytes, kBufferWord3);
     const uint32_t step = 4u * (uint32_t)sk * (uint32_t)sizeof(typename VS::T);
     auto fetch = [&](int p, const Box &b, Raw (&st)[kSlots]) {
         const int q = b.qlo + lane;
@@ -170,7 +178,7 @@ __device__ __forceinline__ void sweep_tile(const DevGeom &g, const TileRec &T, i
 #pragma unroll
                 for (int s = 0; s < kSlots; ++s)
                     if (live & (1u << s))
-                        st[s] = VS::raw_at(v, off0 + (uint32_t)s * step);
+                        st[s] = VS::raw_at(src, off0 + (uint32_t)s * step);
             }
         }
     };
@@ -275,12 +283,14 @@ struct SweepArgs {
 };
 
 // At most five waves per SIMD: with more resident tiles the planes' boxes of
-// different tiles compete for the caches (clinical case: 15.3 ms at six
-// waves, 13.5 ms at five, 14.5 ms at four).
+// different tiles compete for the caches (clinical case, earlier build:
+// 15.3 ms at six waves, 13.5 ms at five, 14.5 ms at four).  At the current
+// register count the occupancy is four; five would need 96 VGPRs, which
+// spills.
 template <class VS, class SS, int RC>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 5)))
 forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
-              typename SS::T *__restrict__ sino)
+              const typename VS::T *__restrict__ volt, typename SS::T *__restrict__ sino)
 {
     extern __shared__ float lds[];
     // XCD-contiguous tile order: workgroups are dealt to the 8 XCDs round
@@ -294,7 +304,8 @@ forward_sweep(SweepArgs A, const typename VS::T *__restrict__ vol,
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
-    sweep_tile<VS, SS, RC>(A.g, T, A.R, A.tub, vol + ch * nvox, sino + ch * nsino, lds);
+    sweep_tile<VS, SS, RC>(A.g, T, A.R, A.tub, vol + ch * nvox, volt + ch * nvox,
+                           sino + ch * nsino, lds);
 }
 
 // ---- batched forward: one launch over all (case, tile) items ----------------
@@ -334,11 +345,42 @@ forward_batch(BatchFwdArgs B)
     // cases with the usual rays per thread take the sweep specialised for it
     // (a uniform branch; the bits do not depend on the variant)
     if (C.R == kMaxR)
-        sweep_tile<VS, SS, kMaxR>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
+        sweep_tile<VS, SS, kMaxR>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol, nullptr,
                                   (typename SS::T *)C.sino, lds);
     else
-        sweep_tile<VS, SS>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
+        sweep_tile<VS, SS>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol, nullptr,
                            (typename SS::T *)C.sino, lds);
+}
+
+// out[s][x][y] = in[s][y][x] for the n_slices (channel x z) slices of a
+// volume: 32 x 32 tiles through LDS, both sides' accesses along rows.
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+transpose_xy(const T *__restrict__ in, T *__restrict__ out, int nx, int ny, int n_slices)
+{
+    __shared__ T tile[32][33];
+    const int tx = (nx + 31) >> 5;
+    const int x0 = (blockIdx.x % tx) * 32, y0 = (blockIdx.x / tx) * 32;
+    const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8
+    const size_t plane = (size_t)nx * ny;
+    for (int sl = blockIdx.y; sl < n_slices; sl += gridDim.y) {
+        const T *src = in + sl * plane;
+        T *dst = out + sl * plane;
+        __syncthreads();   // the previous slice's readers of the tile are done
+#pragma unroll
+        for (int j = ly; j < 32; j += 8) {
+            const int x = x0 + lx, y = y0 + j;
+            if (x < nx && y < ny)
+                tile[j][lx] = src[(size_t)y * nx + x];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = ly; j < 32; j += 8) {
+            const int y = y0 + lx, x = x0 + j;
+            if (x < nx && y < ny)
+                dst[(size_t)x * ny + y] = tile[lx][j];
+        }
+    }
 }
 
 }  // namespace
@@ -350,17 +392,32 @@ hipError_t launch_forward_tiled(const DevGeom &g, const FwdPlan &p, const void *
     SweepArgs A{g, p.tiles, p.R, p.TU == 32 ? 5 : 6};
     const size_t lds = kFwdLds;
     dim3 grid(p.n_tiles, channels), block(kThreads);
-    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
-        using VS = decltype(vs);
-        using SS = decltype(ss);
-        if (p.R == kMaxR)
-            hipLaunchKernelGGL((forward_sweep<VS, SS, kMaxR>), grid, block, lds, s, A,
-                               (const typename VS::T *)vol, (typename SS::T *)sino);
-        else
-            hipLaunchKernelGGL((forward_sweep<VS, SS, 0>), grid, block, lds, s, A,
-                               (const typename VS::T *)vol, (typename SS::T *)sino);
-        return hipGetLastError();
-    });
+    // the volume with x and y swapped, in the library's device buffer, for
+    // the tiles that sweep x planes
+    const size_t nvox = (size_t)g.nx * g.ny * g.nz;
+    ScratchLease lease;
+    hipError_t e = scratch_acquire(nvox * channels * storage_bytes(vt), s, lease);
+    if (e == hipSuccess)
+        e = dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
+            using VS = decltype(vs);
+            using SS = decltype(ss);
+            using T = typename VS::T;
+            const T *x = (const T *)vol;
+            T *xt = (T *)lease.ptr;
+            const int slices = g.nz * channels;
+            const dim3 tgrid(((g.nx + 31) / 32) * ((g.ny + 31) / 32), std::min(slices, 65535));
+            hipLaunchKernelGGL((transpose_xy<T>), tgrid, dim3(kThreads), 0, s, x, xt, g.nx, g.ny,
+                               slices);
+            if (p.R == kMaxR)
+                hipLaunchKernelGGL((forward_sweep<VS, SS, kMaxR>), grid, block, lds, s, A, x, xt,
+                                   (typename SS::T *)sino);
+            else
+                hipLaunchKernelGGL((forward_sweep<VS, SS, 0>), grid, block, lds, s, A, x, xt,
+                                   (typename SS::T *)sino);
+            return hipGetLastError();
+        });
+    const hipError_t r = scratch_release(s, lease);
+    return e != hipSuccess ? e : r;
 }
 
 hipError_t launch_forward_batch(int n, const cbct_geom *const *gs, const void *const *vols,

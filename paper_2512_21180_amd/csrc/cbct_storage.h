@@ -72,6 +72,9 @@ struct F16 {
     __device__ static void st(T *p, size_t i, float v) { p[i] = (_Float16)v; }
 };
 
+// Bytes of one stored element.
+inline size_t storage_bytes(cbct_dtype t) { return t == CBCT_F32 ? 4 : 2; }
+
 // Dispatch a functor templated on <VolStorage, SinoStorage> by runtime codes.
 template <class F>
 inline hipError_t dispatch_storage(cbct_dtype vt, cbct_dtype st, F &&f)
