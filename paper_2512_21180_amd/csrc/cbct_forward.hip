@@ -25,6 +25,7 @@
 
 #include "cbct_internal.h"
 #include "cbct_lds.h"
+#include "cbct_transpose.h"
 #include "cbct_storage.h"
 
 namespace cbct {
@@ -314,7 +315,7 @@ struct FwdCase {
     DevGeom g;
     const TileRec *tiles;
     int R, tub, n_tiles;
-    const void *vol;
+    const void *vol, *volt;   // the volume, and with x and y swapped
     void *sino;
 };
 
@@ -345,42 +346,11 @@ forward_batch(BatchFwdArgs B)
     // cases with the usual rays per thread take the sweep specialised for it
     // (a uniform branch; the bits do not depend on the variant)
     if (C.R == kMaxR)
-        sweep_tile<VS, SS, kMaxR>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol, nullptr,
-                                  (typename SS::T *)C.sino, lds);
+        sweep_tile<VS, SS, kMaxR>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
+                                  (const typename VS::T *)C.volt, (typename SS::T *)C.sino, lds);
     else
-        sweep_tile<VS, SS>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol, nullptr,
-                           (typename SS::T *)C.sino, lds);
-}
-
-// out[s][x][y] = in[s][y][x] for the n_slices (channel x z) slices of a
-// volume: 32 x 32 tiles through LDS, both sides' accesses along rows.
-template <class T>
-__global__ void __launch_bounds__(kThreads)
-transpose_xy(const T *__restrict__ in, T *__restrict__ out, int nx, int ny, int n_slices)
-{
-    __shared__ T tile[32][33];
-    const int tx = (nx + 31) >> 5;
-    const int x0 = (blockIdx.x % tx) * 32, y0 = (blockIdx.x / tx) * 32;
-    const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;   // 32 x 8
-    const size_t plane = (size_t)nx * ny;
-    for (int sl = blockIdx.y; sl < n_slices; sl += gridDim.y) {
-        const T *src = in + sl * plane;
-        T *dst = out + sl * plane;
-        __syncthreads();   // the previous slice's readers of the tile are done
-#pragma unroll
-        for (int j = ly; j < 32; j += 8) {
-            const int x = x0 + lx, y = y0 + j;
-            if (x < nx && y < ny)
-                tile[j][lx] = src[(size_t)y * nx + x];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = ly; j < 32; j += 8) {
-            const int y = y0 + lx, x = x0 + j;
-            if (x < nx && y < ny)
-                dst[(size_t)x * ny + y] = tile[lx][j];
-        }
-    }
+        sweep_tile<VS, SS>(C.g, T, C.R, C.tub, (const typename VS::T *)C.vol,
+                           (const typename VS::T *)C.volt, (typename SS::T *)C.sino, lds);
 }
 
 }  // namespace
@@ -404,10 +374,7 @@ hipError_t launch_forward_tiled(const DevGeom &g, const FwdPlan &p, const void *
             using T = typename VS::T;
             const T *x = (const T *)vol;
             T *xt = (T *)lease.ptr;
-            const int slices = g.nz * channels;
-            const dim3 tgrid(((g.nx + 31) / 32) * ((g.ny + 31) / 32), std::min(slices, 65535));
-            hipLaunchKernelGGL((transpose_xy<T>), tgrid, dim3(kThreads), 0, s, x, xt, g.nx, g.ny,
-                               slices);
+            launch_transpose_xy(x, xt, g.nx, g.ny, g.nz * channels, s);
             if (p.R == kMaxR)
                 hipLaunchKernelGGL((forward_sweep<VS, SS, kMaxR>), grid, block, lds, s, A, x, xt,
                                    (typename SS::T *)sino);
@@ -425,25 +392,38 @@ hipError_t launch_forward_batch(int n, const cbct_geom *const *gs, const void *c
 {
     BatchFwdArgs B{};
     B.n_cases = n;
-    size_t lds = 0;
     int items = 0;
+    size_t off[kMaxBatch], total = 0;   // the cases' transposed volumes in the library's buffer
     for (int i = 0; i < n; ++i) {
         const cbct_geom *g = gs[i];
         B.first[i] = items;
         B.c[i] = FwdCase{g->dev, g->fwd.tiles, g->fwd.R, g->fwd.TU == 32 ? 5 : 6,
-                         g->fwd.n_tiles, vols[i], sinos[i]};
+                         g->fwd.n_tiles, vols[i], nullptr, sinos[i]};
         items += g->fwd.n_tiles;
-        lds = kFwdLds;
+        off[i] = total;
+        total += ((size_t)g->dev.nx * g->dev.ny * g->dev.nz * storage_bytes(vt) + 255) & ~(size_t)255;
     }
     B.first[n] = items;
     B.n_items = items;
     const int grid = (items + 7) / 8 * 8;
-    return dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
-        using VS = decltype(vs);
-        using SS = decltype(ss);
-        hipLaunchKernelGGL((forward_batch<VS, SS>), dim3(grid), dim3(kThreads), lds, s, B);
-        return hipGetLastError();
-    });
+    ScratchLease lease;
+    hipError_t e = scratch_acquire(total, s, lease);
+    if (e == hipSuccess)
+        e = dispatch_storage(vt, st, [&](auto vs, auto ss) -> hipError_t {
+            using VS = decltype(vs);
+            using SS = decltype(ss);
+            using T = typename VS::T;
+            for (int i = 0; i < n; ++i) {
+                T *xt = (T *)((char *)lease.ptr + off[i]);
+                launch_transpose_xy((const T *)vols[i], xt, gs[i]->dev.nx, gs[i]->dev.ny,
+                                    gs[i]->dev.nz, s);
+                B.c[i].volt = xt;
+            }
+            hipLaunchKernelGGL((forward_batch<VS, SS>), dim3(grid), dim3(kThreads), kFwdLds, s, B);
+            return hipGetLastError();
+        });
+    const hipError_t r = scratch_release(s, lease);
+    return e != hipSuccess ? e : r;
 }
 
 }  // namespace cbct

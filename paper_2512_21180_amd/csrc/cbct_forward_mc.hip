@@ -32,6 +32,7 @@
 
 #include "cbct_internal.h"
 #include "cbct_lds.h"
+#include "cbct_transpose.h"
 #include "cbct_storage.h"
 
 namespace cbct {
@@ -80,6 +81,7 @@ struct McGroup {
     const TileRec *tiles;
     int R, tub, n_tiles;
     const void *vg;      // [nz][ny][nx] vectors of C channels
+    const void *vgt;     // the same with x and y swapped, [nz][nx][ny]
     float *sino[kMaxMcChannels];
 };
 
@@ -127,10 +129,13 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
     const float kbB0 = fmaf(cB.t0, zA, g.Kb), ksB0 = cB.tau * zA;
     const float kbB1 = fmaf(cB.t0, zB, g.Kb), ksB1 = cB.tau * zB;
 
+    // tiles that sweep x planes stage from the transposed packed volume, so
+    // a box row is contiguous there too (as in the single-channel sweep)
     const bool xp = T.cls == 0;
     const int nq = xp ? g.ny : g.nx;
-    const int sp = xp ? 1 : g.nx;
-    const int sq = xp ? g.nx : 1;
+    const void *src = xp ? M.vgt : M.vg;
+    const int sp = xp ? g.ny : g.nx;
+    const int sq = 1;
     const int sk = g.nx * g.ny;
 
     struct Box {
@@ -168,7 +173,7 @@ __device__ __forceinline__ void sweep_tile_mc(const McGroup &M, const TileRec &T
     // kernel runs).
     const uint32_t vbytes = (uint32_t)sk * (uint32_t)g.nz * (uint32_t)sizeof(V0);
     const __amdgpu_buffer_rsrc_t vres =
-        __builtin_amdgcn_make_buffer_rsrc((void *)M.vg, (short)0, (int)vbytes, kBufferWord3);
+        __builtin_amdgcn_make_buffer_rsrc((void *)src, (short)0, (int)vbytes, kBufferWord3);
     const uint32_t step = 4u * (uint32_t)sk * (uint32_t)sizeof(V0);
     auto fetch = [&](int p, const Box &b, V0 (&st0)[kSlots]) {
         const int q = b.qlo + lane;
@@ -406,7 +411,7 @@ hipError_t launch_forward_mc(int n, const cbct_geom *const *gs, const float *con
         if (forward_mc_max_channels(g) < C)
             return hipErrorInvalidValue;   // 65 x 32 boxes of 4 channels exceed 64 KB of LDS
         const size_t nvox = (size_t)g->desc.nx * g->desc.ny * g->desc.nz;
-        off[i + 1] = off[i] + (nvox * C * sizeof(float) + 255) / 256 * 256;
+        off[i + 1] = off[i] + 2 * ((nvox * C * sizeof(float) + 255) / 256 * 256);   // + transposed
     }
     McArgs B{};
     B.n_groups = n;
@@ -420,13 +425,19 @@ hipError_t launch_forward_mc(int n, const cbct_geom *const *gs, const float *con
             for (int ch = 0; ch < C; ++ch)
                 P.in[ch] = vols[(size_t)i * C + ch];
             P.out = (char *)lease.ptr + off[i];
+            void *outt = (char *)lease.ptr + (off[i] + off[i + 1]) / 2;
             const dim3 grid((unsigned)((P.n + kThreads - 1) / kThreads));
-            if (C == 4)
+            const int nx = g->desc.nx, ny = g->desc.ny, nz = g->desc.nz;
+            if (C == 4) {
                 hipLaunchKernelGGL(pack_channels<4>, grid, dim3(kThreads), 0, s, P);
-            else
+                launch_transpose_xy((const float4 *)P.out, (float4 *)outt, nx, ny, nz, s);
+            } else {
                 hipLaunchKernelGGL(pack_channels<2>, grid, dim3(kThreads), 0, s, P);
+                launch_transpose_xy((const float2 *)P.out, (float2 *)outt, nx, ny, nz, s);
+            }
             e = hipGetLastError();
             B.grp[i].vg = P.out;
+            B.grp[i].vgt = outt;
         }
         if (e == hipSuccess)
             e = launch_mc_groups(B, gs, sinos, C, n, s);
