@@ -56,7 +56,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # device copy), valid for the kernel sources whose hash it records.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "projector_c2_f32_hbm_traffic.json")
 KERNEL_SOURCES = ("cbct_adjoint.hip", "cbct_forward.hip", "cbct_internal.h", "cbct_storage.h", "cbct_lds.h",
-                  "cbct_plan.cpp", "cbct_geom.cpp", "cbct_api.cpp", "cbct_scratch.cpp")
+                  "cbct_transpose.h", "cbct_plan.cpp", "cbct_geom.cpp", "cbct_api.cpp", "cbct_scratch.cpp")
 # The adjoint operator is two launches: the ds_weight pre-pass (projection
 # values times each ray's length per plane) and the gather adjoint_brick.
 
