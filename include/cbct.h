@@ -157,7 +157,9 @@ cbct_status cbct_adjoint(const cbct_geom *g, const void *sino, cbct_dtype st,
  * its own geometry handle and buffers (host arrays of n handles and n device
  * pointers), in one launch over all cases' work items (batches of more than
  * 16 cases run as one launch per 16 cases; cases whose geometry takes the
- * one-thread-per-ray kernel are launched on their own).  Results are
+ * one-thread-per-ray kernel are launched on their own).  Like cbct_forward
+ * it first writes each case's volume with x and y swapped into the
+ * library-owned device buffer.  Results are
  * bitwise identical to n separate cbct_forward calls.  With FP32 storage, cases that share one
  * handle (e.g. the channels of a stack, as in Alg. 1) are instead cut into
  * groups of four or two that share each sample's geometry (packed into a
