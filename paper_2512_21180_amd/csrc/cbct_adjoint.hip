@@ -56,6 +56,11 @@ namespace cbct {
 namespace {
 
 constexpr int kThreads = 256;
+// Window rows per wave and staging batch (loads in flight per lane).
+constexpr int kStageRows = 24;
+// Columns of at least 4 kStageRows rows take the staging whose batches stay
+// inside the column (bricks of KV = 4, the clinical windows).
+constexpr bool adj_tall(int KV, int HS) { return KV == 4 && HS >= 4 * kStageRows; }
 
 struct BrickArgs {
     DevGeom g;
@@ -236,12 +241,12 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&lo)[2][
 // the one below, on each axis) are added in a fixed order through LDS.
 // `lds` holds the panel window, column-major ([W][HS], HS = 2 mod 4, which
 // suits the gather's reads), and the column table; then the exchange.
-template <class VS, int KV>
+template <class VS, int KV, bool TALL>
 __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const float *ws,
                                              typename VS::T *vol, float *lds)
 {
     constexpr int kBK = 4 * KV;
-    constexpr int kSB = 24;  // rows per staging batch (loads in flight)
+    constexpr int kSB = kStageRows;
     const DevGeom &g = A.g;
     const int HS = A.HS;
     float *yt = lds;                                    // ds-weighted panel window
@@ -320,6 +325,21 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const fl
             __builtin_amdgcn_make_buffer_rsrc((void *)proj, (short)0, (V1 - V0 + 1) * g.nu * 4,
                                               kBufferWord3);
         const int row_bytes = 4 * g.nu;
+        // A batch's kSB rows (stride 4) stay inside the column (HS rows).  In
+        // tall columns (TALL: HS >= 4 kSB, the clinical windows) a batch that
+        // would run past the column starts lower instead, at the last row
+        // of the wave's residue class that keeps it inside (it then stores
+        // some rows of the wave's previous batch again, with the same
+        // values), so its stores take immediate offsets from one address.
+        // Otherwise the rows past Hs (zeros) all go to row HS - 1, a spare
+        // row no tap reads (HS > H >= Hs).  Either way every store is
+        // unconditional, so no load can be moved behind the wait for the
+        // others.
+        int vtop = 0;
+        if constexpr (TALL) {
+            const int top = HS - 1 - 4 * (kSB - 1);   // >= 3 in tall columns
+            vtop = top - ((top - w) & 3);             // largest start = w mod 4
+        }
         for (int uu = lane; uu < Wc; uu += 64) {
             // one wave also writes the column table (uniform branches); its
             // load is issued with the rows' and stored after them, so that
@@ -332,11 +352,12 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const fl
             const int cb = 4 * (U0 + uu);   // byte offset of the column in a row
             float *dst = yt + (size_t)uu * HS;
             for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
+                const int vb = TALL ? min(vv0, vtop) : vv0;
                 // the batch's first row for this lane, kept in one register
                 // (the empty asm stops the compiler from hoisting kSB lane
                 // offsets out of the loop, which costs kSB registers); each
                 // load adds a wave-uniform row offset
-                int off = cb + vv0 * row_bytes;
+                int off = cb + vb * row_bytes;
                 asm volatile("" : "+v"(off));
                 float val[kSB];
 #pragma unroll
@@ -344,12 +365,16 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const fl
                     val[jj] = __builtin_bit_cast(
                         float, __builtin_amdgcn_raw_buffer_load_b32(
                                    rows, off + 4 * jj * row_bytes, 0, 0));
-                // rows past Hs (zeros) all go to row HS - 1, a spare row no
-                // tap reads (HS > H >= Hs): with every store unconditional no
-                // load can be moved behind the wait for the others
+                if constexpr (TALL) {
+                    float *d = dst + vb;
 #pragma unroll
-                for (int jj = 0; jj < kSB; ++jj)
-                    dst[min(vv0 + 4 * jj, HS - 1)] = val[jj];
+                    for (int jj = 0; jj < kSB; ++jj)
+                        d[4 * jj] = val[jj];
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < kSB; ++jj)
+                        dst[min(vv0 + 4 * jj, HS - 1)] = val[jj];
+                }
             }
             if (w == 0)
                 cr[uu] = ctab;
@@ -447,7 +472,7 @@ __host__ __device__ inline int slots_per_xcd(const BrickArgs &A)
     return A.nbx * A.nbz * ((A.nby + 7) / 8);
 }
 
-template <class VS, int KV>
+template <class VS, int KV, bool TALL>
 __global__ void __launch_bounds__(kThreads)
 adjoint_brick(BrickArgs A, const float *__restrict__ ws, typename VS::T *__restrict__ vol)
 {
@@ -458,7 +483,7 @@ adjoint_brick(BrickArgs A, const float *__restrict__ ws, typename VS::T *__restr
     const int ch = blockIdx.y;
     const size_t nvox = (size_t)A.g.nx * A.g.ny * A.g.nz;
     const size_t nsino = (size_t)A.g.n_angles * A.g.nv * A.g.nu;
-    gather_brick<VS, KV>(A, b, ws + ch * nsino, vol + ch * nvox, lds);
+    gather_brick<VS, KV, TALL>(A, b, ws + ch * nsino, vol + ch * nvox, lds);
 }
 
 // The ds-weighted copy of a sinogram that the bricks stage from:
@@ -512,9 +537,9 @@ adjoint_batch(BatchAdjArgs B)
         return;
     auto *vs = (typename VS::T *)C.vol;
     switch (C.A.KV) {   // uniform over the workgroup
-    case 4: gather_brick<VS, 4>(C.A, b, C.ws, vs, lds); break;
-    case 2: gather_brick<VS, 2>(C.A, b, C.ws, vs, lds); break;
-    default: gather_brick<VS, 1>(C.A, b, C.ws, vs, lds); break;
+    case 4: gather_brick<VS, 4, false>(C.A, b, C.ws, vs, lds); break;
+    case 2: gather_brick<VS, 2, false>(C.A, b, C.ws, vs, lds); break;
+    default: gather_brick<VS, 1, false>(C.A, b, C.ws, vs, lds); break;
     }
 }
 
@@ -566,12 +591,14 @@ hipError_t launch_adjoint_brick(const DevGeom &g, const AdjPlan &p, const void *
             const size_t lds = brick_lds(p);
             const float *w = (const float *)lease.ptr;
             auto *x = (typename VS::T *)vol;
-            if (p.KV == 4)
-                hipLaunchKernelGGL((adjoint_brick<VS, 4>), grid, block, lds, s, A, w, x);
+            if (adj_tall(p.KV, p.WS))
+                hipLaunchKernelGGL((adjoint_brick<VS, 4, true>), grid, block, lds, s, A, w, x);
+            else if (p.KV == 4)
+                hipLaunchKernelGGL((adjoint_brick<VS, 4, false>), grid, block, lds, s, A, w, x);
             else if (p.KV == 2)
-                hipLaunchKernelGGL((adjoint_brick<VS, 2>), grid, block, lds, s, A, w, x);
+                hipLaunchKernelGGL((adjoint_brick<VS, 2, false>), grid, block, lds, s, A, w, x);
             else
-                hipLaunchKernelGGL((adjoint_brick<VS, 1>), grid, block, lds, s, A, w, x);
+                hipLaunchKernelGGL((adjoint_brick<VS, 1, false>), grid, block, lds, s, A, w, x);
             return hipGetLastError();
         });
     const hipError_t r = scratch_release(s, lease);

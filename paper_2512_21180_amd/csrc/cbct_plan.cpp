@@ -227,7 +227,9 @@ AdjPlan adjoint_plan(const cbct_geom *g, const WinTable &t, int bk, int channels
     // over the LDS banks best: at the clinical size 23.0 ms for the adjoint
     // against 24.0 ms with odd strides, which would instead spare the
     // staging's row writes a two-way conflict.  The stride exceeds H: the
-    // staging writes the rows of a batch past the window to the spare row.
+    // staging writes the rows of a batch past the window to the rows above
+    // it (tall columns) or to the spare row (short ones), never past the
+    // column.
     int WS = H + 1 + (5 - H % 4) % 4;
     size_t lds = (size_t)W * WS * channels * sizeof(float) + (size_t)W * 4 * sizeof(float);
     if (W > 0 && lds <= budget && NT <= kMaxTaps) {

@@ -80,7 +80,11 @@ WIDE_PANEL = W.geometry(3, 40000, 16, 0.01, 0.01, 16, 16, 8, 0.05, off_u=-150.0)
 # a 9 mm slab under a 90 mm panel: most rays pass above or below the volume,
 # so the forward's staged boxes reach past both its ends (read as zeros)
 THIN_SLAB = W.geometry(10, 60, 90, 1.0, 1.0, 30, 26, 6, 1.5, off_u=4.0, off_v=3.0)
+# the clinical panel over a 160^3 volume at 2 mm: adjoint windows of at least
+# 96 rows, whose staging batches stay inside the window's columns
+TALL_WINDOWS = W.cropped(W.C2, n_angles=3, n=160)
 CASES = {
+    "tall_windows": TALL_WINDOWS,
     "thin_slab": THIN_SLAB,
     "fallback_fwd": FINE_VOX,
     "fallback_adj": COARSE_VOX,

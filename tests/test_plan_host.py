@@ -471,3 +471,43 @@ def test_window_columns_pack_above_32767():
         assert np.all(u1 - (u01 & 0xFFFF)[seen] + 1 <= h.info[6])
     finally:
         h.close()
+
+
+def _staged_rows(HS, Hs, w, sb=24):
+    """Rows of one window column that wave w stores in the adjoint's staging
+    of tall columns (HS >= 4 sb): batches of sb rows at stride 4 from row w,
+    a batch that would pass the column moved down to the last start of the
+    wave's residue class that keeps it inside."""
+    top = HS - 1 - 4 * (sb - 1)
+    vtop = top - ((top - w) & 3)
+    rows = []
+    for vv0 in range(w, Hs, 4 * sb):
+        vb = min(vv0, vtop)
+        rows += [vb + 4 * j for j in range(sb)]
+    return rows
+
+
+@pytest.mark.parametrize("HS", [96, 97, 98, 99, 114, 118, 150, 190, 191, 192, 193, 250])
+def test_tall_window_staging_stays_in_the_column(HS):
+    """Every row the waves of a tall column store lies in [0, HS), each wave
+    stores only rows of its own residue class, and the rows below Hs (every
+    row a tap may read) are all stored, for every staged height Hs < HS."""
+    for Hs in range(1, HS):
+        seen = set()
+        for w in range(4):
+            rows = _staged_rows(HS, Hs, w)
+            assert all(0 <= r <= HS - 1 for r in rows), (HS, Hs, w)
+            assert all(r % 4 == w for r in rows), (HS, Hs, w)
+            seen.update(rows)
+        assert set(range(Hs)) <= seen, (HS, Hs)
+
+
+def test_tall_windows_at_clinical_size():
+    """The clinical plan's window column (118 rows) takes the tall-column
+    staging; the small cases' columns (34 and 54 rows) do not."""
+    for name, tall in (("c2", True), ("c1", False), ("c4", False)):
+        h = Host(GEOMS[name])
+        try:
+            assert (h.info[10] == 4 and h.info[8] >= 96) == tall, name
+        finally:
+            h.close()
