@@ -231,6 +231,50 @@ __device__ __forceinline__ void gather_angle(const GatherIn &in, float (&lo)[2][
     }
 }
 
+// Stage one angle's panel window into a tall column layout (HS >= 4 SB):
+// Wc columns (from U0) x Hs rows of the ds-weighted projection, whose rows
+// V0 .. V1 the buffer resource `rows` holds, into yt, column-major with
+// stride HS, and the columns' records into cr.  Columns on lanes, rows on
+// waves (stride 4), SB rows per wave and batch.  A batch that would run past
+// the column starts lower instead, at the last row of the wave's residue
+// class that keeps it inside (it then stores some rows of the wave's
+// previous batch again, with the same values), so its stores take immediate
+// offsets from one address.
+template <int SB>
+__device__ __forceinline__ void stage_tall(const DevGeom &g, int a, __amdgpu_buffer_rsrc_t rows,
+                                           int U0, int Wc, int Hs, int HS, int w, int lane,
+                                           float *yt, float4 *cr)
+{
+    const int row_bytes = 4 * g.nu;
+    const int top = HS - 1 - 4 * (SB - 1);   // >= 3 in tall columns
+    const int vtop = top - ((top - w) & 3);  // largest start = w mod 4
+    for (int uu = lane; uu < Wc; uu += 64) {
+        float4 ctab;   // one wave writes the column table (see gather_brick)
+        if (w == 0) {
+            const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
+            ctab = make_float4(col.pb, col.ps, col.t0, col.tau);
+        }
+        const int cb = 4 * (U0 + uu);   // byte offset of the column in a row
+        float *dst = yt + (size_t)uu * HS;
+        for (int vv0 = w; vv0 < Hs; vv0 += 4 * SB) {
+            const int vb = min(vv0, vtop);
+            int off = cb + vb * row_bytes;   // kept in one register (see gather_brick)
+            asm volatile("" : "+v"(off));
+            float val[SB];
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                val[jj] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(rows, off + 4 * jj * row_bytes, 0, 0));
+            float *d = dst + vb;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                d[4 * jj] = val[jj];
+        }
+        if (w == 0)
+            cr[uu] = ctab;
+    }
+}
+
 // Gather one brick (index b): bricks hold kAdjBI x kAdjBJ x 4 KV output
 // voxels.  Lane roles (wave w owns the KV voxel layers from 4 KV (brick z) +
 // KV w up): on x planes lane l takes plane i0 + l % 8 and in-plane segment
@@ -312,72 +356,70 @@ __device__ __forceinline__ void gather_brick(const BrickArgs &A, int b, const fl
         const int VS1 = max(V1 - NT + 1, V0);
 
         __syncthreads();   // previous angle's readers are done
-        // Columns on lanes, rows on waves (stride 4).  The loads of kSB rows
-        // are issued before any of them is used, so their latencies overlap
-        // instead of adding up row after row.  They go through a buffer
-        // resource holding exactly rows V0 .. V1 of this projection: the
-        // range check returns zero for every row past V1 (the window's zero
-        // rows and a batch's rows past Hs) without touching memory, so no
-        // load needs a test of its own.  Byte offsets within the rows are
-        // 32-bit (nv nu < 2^24).
+        // Columns on lanes, rows on waves (stride 4).  The loads of a batch
+        // of rows are issued before any of them is used, so their latencies
+        // overlap instead of adding up row after row.  They go through a
+        // buffer resource holding exactly rows V0 .. V1 of this projection:
+        // the range check returns zero for every row past V1 (the window's
+        // zero rows and a batch's rows past Hs) without touching memory, so
+        // no load needs a test of its own.  Byte offsets within the rows are
+        // 32-bit (nv nu < 2^24).  Every store is unconditional, so no load
+        // can be moved behind the wait for the others; one wave also writes
+        // the column table, its load issued with the rows' and stored after
+        // them, so that wave does not wait for it before issuing its row
+        // loads.  The batch's first row offset for a lane is kept in one
+        // register (the empty asm stops the compiler from hoisting a lane
+        // offset per row out of the loop, which costs a register per row);
+        // each load adds a wave-uniform row offset.
         const float *proj = ws + ((size_t)a * g.nv + V0) * g.nu;   // row V0, ds-weighted
         const __amdgpu_buffer_rsrc_t rows =
             __builtin_amdgcn_make_buffer_rsrc((void *)proj, (short)0, (V1 - V0 + 1) * g.nu * 4,
                                               kBufferWord3);
-        const int row_bytes = 4 * g.nu;
-        // A batch's kSB rows (stride 4) stay inside the column (HS rows).  In
-        // tall columns (TALL: HS >= 4 kSB, the clinical windows) a batch that
-        // would run past the column starts lower instead, at the last row
-        // of the wave's residue class that keeps it inside (it then stores
-        // some rows of the wave's previous batch again, with the same
-        // values), so its stores take immediate offsets from one address.
-        // Otherwise the rows past Hs (zeros) all go to row HS - 1, a spare
-        // row no tap reads (HS > H >= Hs).  Either way every store is
-        // unconditional, so no load can be moved behind the wait for the
-        // others.
-        int vtop = 0;
         if constexpr (TALL) {
-            const int top = HS - 1 - 4 * (kSB - 1);   // >= 3 in tall columns
-            vtop = top - ((top - w) & 3);             // largest start = w mod 4
-        }
-        for (int uu = lane; uu < Wc; uu += 64) {
-            // one wave also writes the column table (uniform branches); its
-            // load is issued with the rows' and stored after them, so that
-            // wave does not wait for it before issuing its row loads
-            float4 ctab;
-            if (w == 0) {
-                const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
-                ctab = make_float4(col.pb, col.ps, col.t0, col.tau);
-            }
-            const int cb = 4 * (U0 + uu);   // byte offset of the column in a row
-            float *dst = yt + (size_t)uu * HS;
-            for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
-                const int vb = TALL ? min(vv0, vtop) : vv0;
-                // the batch's first row for this lane, kept in one register
-                // (the empty asm stops the compiler from hoisting kSB lane
-                // offsets out of the loop, which costs kSB registers); each
-                // load adds a wave-uniform row offset
-                int off = cb + vb * row_bytes;
-                asm volatile("" : "+v"(off));
-                float val[kSB];
-#pragma unroll
-                for (int jj = 0; jj < kSB; ++jj)
-                    val[jj] = __builtin_bit_cast(
-                        float, __builtin_amdgcn_raw_buffer_load_b32(
-                                   rows, off + 4 * jj * row_bytes, 0, 0));
-                if constexpr (TALL) {
-                    float *d = dst + vb;
+            // Batches no longer than the window needs: SB rows per wave
+            // cover 4 SB rows, SB = 16 up to 64 rows, 20 up to 80, else 24
+            // (and more batches past 96 rows), so fewer rows past the window
+            // are loaded and stored.  (Seven lengths from 8 to 24 saved a
+            // further tenth of the staged rows but cost registers and were
+            // slower.)
+            if (Hs <= 64)
+                stage_tall<16>(g, a, rows, U0, Wc, Hs, HS, w, lane, yt, cr);
+            else if (Hs <= 80)
+                stage_tall<20>(g, a, rows, U0, Wc, Hs, HS, w, lane, yt, cr);
+            else
+                stage_tall<kSB>(g, a, rows, U0, Wc, Hs, HS, w, lane, yt, cr);
+        } else {
+            // Short columns: batches of kSB rows per wave whose rows past Hs
+            // (zeros) all go to row HS - 1, a spare row no tap reads (HS > H
+            // >= Hs).  Written out here rather than in a function like
+            // stage_tall, so these kernels compile as they did before the
+            // tall variant existed (the call changed their register
+            // allocation).
+            const int row_bytes = 4 * g.nu;
+            for (int uu = lane; uu < Wc; uu += 64) {
+                float4 ctab;
+                if (w == 0) {
+                    const ColRec col = g.cols[(size_t)a * g.nu + U0 + uu];
+                    ctab = make_float4(col.pb, col.ps, col.t0, col.tau);
+                }
+                const int cb = 4 * (U0 + uu);
+                float *dst = yt + (size_t)uu * HS;
+                for (int vv0 = w; vv0 < Hs; vv0 += 4 * kSB) {
+                    int off = cb + vv0 * row_bytes;
+                    asm volatile("" : "+v"(off));
+                    float val[kSB];
 #pragma unroll
                     for (int jj = 0; jj < kSB; ++jj)
-                        d[4 * jj] = val[jj];
-                } else {
+                        val[jj] = __builtin_bit_cast(
+                            float, __builtin_amdgcn_raw_buffer_load_b32(
+                                       rows, off + 4 * jj * row_bytes, 0, 0));
 #pragma unroll
                     for (int jj = 0; jj < kSB; ++jj)
                         dst[min(vv0 + 4 * jj, HS - 1)] = val[jj];
                 }
+                if (w == 0)
+                    cr[uu] = ctab;
             }
-            if (w == 0)
-                cr[uu] = ctab;
         }
         __syncthreads();
 

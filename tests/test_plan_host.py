@@ -487,15 +487,21 @@ def _staged_rows(HS, Hs, w, sb=24):
     return rows
 
 
+def _tall_batch_rows(Hs):
+    """Rows per wave and batch of the tall-column staging for Hs staged rows."""
+    return 16 if Hs <= 64 else 20 if Hs <= 80 else 24
+
+
 @pytest.mark.parametrize("HS", [96, 97, 98, 99, 114, 118, 150, 190, 191, 192, 193, 250])
 def test_tall_window_staging_stays_in_the_column(HS):
     """Every row the waves of a tall column store lies in [0, HS), each wave
     stores only rows of its own residue class, and the rows below Hs (every
-    row a tap may read) are all stored, for every staged height Hs < HS."""
+    row a tap may read) are all stored, for every staged height Hs < HS and
+    the batch length the kernel takes for it."""
     for Hs in range(1, HS):
         seen = set()
         for w in range(4):
-            rows = _staged_rows(HS, Hs, w)
+            rows = _staged_rows(HS, Hs, w, _tall_batch_rows(Hs))
             assert all(0 <= r <= HS - 1 for r in rows), (HS, Hs, w)
             assert all(r % 4 == w for r in rows), (HS, Hs, w)
             seen.update(rows)
