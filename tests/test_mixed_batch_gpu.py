@@ -92,6 +92,21 @@ def test_adjoint_storage_bounds(dev, oracle, st, vt):
     _check(x, ref, st, vt, f"adjoint {st}->{vt}")
 
 
+@pytest.mark.parametrize("st,vt", [("bf16", "bf16"), ("f16", "f16")])
+def test_adjoint_storage_bounds_tall_windows(dev, oracle, st, vt):
+    """The clinical panel over a 160^3 volume: adjoint windows of at least 96
+    rows, which take the gather variant whose staging batches stay inside
+    the window's columns, with 16-bit sinogram and volume."""
+    torch, cbct, tmap = dev
+    g = W.cropped(W.C2, n_angles=3, n=160)
+    print(f"[mixed] adjoint {st}->{vt}, tall windows", flush=True)
+    geo = cbct.Geometry(g)
+    y = np.abs(W.random_sino(g, 7))
+    yg = torch.tensor(y, dtype=torch.float32, device="cuda").to(tmap[st])
+    x = cbct.adjoint(geo, yg, out_dtype=tmap[vt]).double().cpu().numpy()
+    _check(x, oracle.adjoint(g, y), st, vt, f"adjoint {st}->{vt} (tall windows)")
+
+
 def test_c3_batch_bf16(dev, oracle):
     """Twelve cases (96^3..256^3, 2-4 mm, 90-360 angles, 256^2..512^2 panels)
     in BF16 storage: one batched call each way, bitwise equal to single
