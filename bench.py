@@ -11,8 +11,8 @@ Also measured (key "recon"): the metric's second half, seconds to a fixed
 PSNR for the learned primal-dual net against CGLS on one held-out phantom
 (see recon_comparison).
 
-Prints one JSON line.  `--gpus N` with N > 1 exits: this build runs on one
-GPU only.
+Prints one JSON line.  `--gpus N` with N > 1 exits: the benchmark runs on
+one GPU only.
 
 `--workload` selects another case for the same measurement (the default is
 the clinical-size FP32 case above; the others skip the reconstruction
@@ -601,7 +601,7 @@ def main():
         print(json.dumps({k: v["traffic_bytes"] for k, v in rec["kernels"].items()}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on a single GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on a single GPU; --gpus {args.gpus} is not supported "
               "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 

@@ -1,5 +1,5 @@
 """bench.py's command-line contract, checked without a GPU: more than one GPU
-is refused with a message and exit status 2 (this build runs on one GPU),
+is refused with a message and exit status 2 (the benchmark runs on one GPU),
 and the options parse."""
 import os
 import subprocess
